@@ -1,0 +1,123 @@
+/*
+ * hydroagg.h -- C ABI of libhydroagg.so: the aggregated FP64 sub-grid hydro
+ * step on MI355X (gfx950).
+ *
+ * Operation.  One forward-Euler stage of the ideal-gas Euler equations on a
+ * batch of independent octree sub-grids (the paper's Section IV-B "Hydro
+ * Solver": piecewise-parabolic reconstruction, central-upwind fluxes at the
+ * cell-face centres, flux-divergence update; Section V-A: an N^3 sub-grid
+ * stored with a 3-cell ghost layer, (N+6)^3 cells per field).  The batch is
+ * executed by ONE aggregated kernel launch per sub-grid shape class instead
+ * of one launch per sub-grid (the paper's strategy 3, Section V-D).  gamma is
+ * fixed at 5/3.
+ *
+ * Memory layout of one sub-grid (both u_in and u_out): float64, structure of
+ * arrays [nfields][M][M][M], M = n + 6, x fastest, linear index
+ * ((f*M + z)*M + y)*M + x.  Interior cells are x, y, z in [3, n+3).
+ * Fields: 0 rho, 1 sx, 2 sy, 3 sz, 4 egas (total energy density), 5 tau
+ * (passive entropy tracer), 6..10 partial densities of 5 species (nfields 11).
+ *
+ * Ownership.  All data pointers are DEVICE pointers owned by the caller; the
+ * library never frees them and never keeps them past the completion of the
+ * work that names them.  The library owns its descriptor tables, pinned
+ * staging, events and streams, all created at initialisation / create time;
+ * no device allocation happens on the step path.
+ *
+ * Asynchrony.  Calls only enqueue work.  Results are valid once the stream
+ * (hydro_step) or the ticket (aggregator) has completed.  The caller keeps
+ * every buffer alive until then.
+ *
+ * Errors.  Every call returns 0 on success or a negative code below; the
+ * message of the last failure on the calling thread is hydro_last_error().
+ */
+#ifndef HYDROAGG_H
+#define HYDROAGG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HYDRO_OK 0
+#define HYDRO_EINVAL (-1)  /* bad argument (see each call)                   */
+#define HYDRO_EHIP (-2)    /* a HIP runtime call failed; text in last_error  */
+#define HYDRO_ENOMEM (-3)  /* no descriptor / slab space left                */
+#define HYDRO_EAGAIN (-4)  /* admission refused (HBM budget); retry later    */
+
+#define HYDRO_GHOST 3
+
+/* One sub-grid task: 32 bytes. */
+typedef struct {
+  const double *u_in; /* device; [nfields][M][M][M]; read-only                 */
+  double *u_out;      /* device; same shape; only the interior n^3 is written;
+                         must not alias u_in                                  */
+  int32_t n;          /* interior edge: 8, 12 or 16                            */
+  int32_t nfields;    /* 6 or 11                                               */
+  int32_t level;      /* octree level: cell width dx_s = dx * 2^-level, 0..30  */
+  int32_t reserved;   /* must be 0                                             */
+} hydro_subgrid_t;
+
+/*
+ * hydro_step -- one stage for `count` sub-grids (paper Section IV-B), as one
+ * aggregated launch per (n, nfields) class present in the batch.
+ *   sg       host array of `count` descriptors (copied before return).
+ *   dt       time-step, >= 0 and finite.  dt = 0 leaves the interior equal to
+ *            u_in and still produces amax (used to pick the Courant dt).
+ *   dx       cell width at level 0, > 0 and finite.
+ *   amax_dev device array of `count` doubles or NULL: amax_dev[s] = max over
+ *            all 3(n+1)n^2 faces of sub-grid s of max(a+, -a-), the largest
+ *            signal speed (the quantity behind the Courant limit, Sec. IV-B).
+ *   stream   hipStream_t to enqueue on (NULL = default stream).
+ * Per sub-grid: U_out = U - dt/dx_s * sum_d (F_{d,i+1/2} - F_{d,i-1/2}) on
+ * the interior; ghost cells of u_out are never written.
+ * Errors: HYDRO_EINVAL for sg == NULL with count > 0, count < 0, n not in
+ * {8,12,16}, nfields not in {6,11}, level outside 0..30, reserved != 0, NULL
+ * or aliased u_in/u_out, dt < 0 or not finite, dx <= 0 or not finite;
+ * HYDRO_EHIP if a launch or copy fails.  count = 0 is a no-op success.
+ */
+int hydro_step(const hydro_subgrid_t *sg, int32_t count, double dt, double dx,
+               double *amax_dev, void *stream);
+
+/*
+ * hydro_step_each -- the non-aggregated baseline: the same kernel launched
+ * once per sub-grid (the paper's "1 executor, max aggregated 1" setting,
+ * Section VI-B), every launch on `stream`, each carrying its one descriptor
+ * in its kernel arguments.  Same arguments, results and errors as
+ * hydro_step; results are bitwise identical to it.
+ */
+int hydro_step_each(const hydro_subgrid_t *sg, int32_t count, double dt,
+                    double dx, double *amax_dev, void *stream);
+
+/*
+ * Plans: a fixed batch whose descriptor table is uploaded once, for callers
+ * that step the same set of sub-grids repeatedly (every stage of a time-step
+ * on device-resident state).  hydro_plan_create copies `sg` into a
+ * plan-owned device table (this allocates, so it belongs to set-up, not to
+ * the step path).  hydro_plan_step then only launches kernels: one per
+ * (n, nfields) class, with the results and errors of hydro_step.
+ * hydro_plan_launch_graph runs the same launches as ONE hipGraph launch on
+ * `stream` (the graph is built on first use and its kernel parameters are
+ * updated in place when dt, dx or amax_dev change).  A plan may be used from
+ * one host thread at a time; hydro_plan_destroy waits for its work.
+ */
+typedef struct hydro_plan hydro_plan_t;
+int hydro_plan_create(hydro_plan_t **out, const hydro_subgrid_t *sg,
+                      int32_t count);
+int hydro_plan_step(hydro_plan_t *plan, double dt, double dx,
+                    double *amax_dev, void *stream);
+int hydro_plan_launch_graph(hydro_plan_t *plan, double dt, double dx,
+                            double *amax_dev, void *stream);
+int hydro_plan_destroy(hydro_plan_t *plan);
+
+/* Thread-local text of the last error on the calling thread ("" if none). */
+const char *hydro_last_error(void);
+
+/* Library build string (kernel variant, target). */
+const char *hydro_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYDROAGG_H */

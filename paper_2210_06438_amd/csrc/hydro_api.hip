@@ -1,0 +1,424 @@
+// hydro_api.hip -- host side of libhydroagg.so: argument checks, descriptor
+// tables, and the aggregated / per-sub-grid launches of the hydro step.
+//
+// Aggregation (paper Section V-D, strategy 3): a batch of sub-grid tasks is
+// sorted into shape classes (n, nfields) and each class runs as ONE launch in
+// which work-group s steps sub-grid s of the class.  The descriptors go to
+// the device through a library-owned table: a ring of slots, each a pinned
+// host buffer plus a device buffer plus an event, all created once per device
+// at first use (no device allocation or stream creation on the step path,
+// Section V-C).  Small classes carry their descriptors in kernel arguments.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/hydroagg.h"
+#include "hydro_kernel.hpp"
+
+using hydro::ArgDescs;
+using hydro::DevDesc;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_TRY(expr)                                                       \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return fail(HYDRO_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// Shape classes: (n, nfields) -> index.
+constexpr int kEdges[3] = {8, 12, 16};
+constexpr int kFields[2] = {6, 11};
+constexpr int kClasses = 6;
+
+int class_of(int n, int nf) {
+  int e = n == 8 ? 0 : n == 12 ? 1 : n == 16 ? 2 : -1;
+  int f = nf == 6 ? 0 : nf == 11 ? 1 : -1;
+  return (e < 0 || f < 0) ? -1 : e * 2 + f;
+}
+
+// ---- descriptor ring ------------------------------------------------------
+constexpr int kSlots = 8;
+constexpr int kSlotCap = 1 << 16;
+
+struct Slot {
+  DevDesc* host = nullptr;  // pinned
+  DevDesc* dev = nullptr;
+  hipEvent_t done = nullptr;
+  bool used = false;
+};
+
+struct DeviceState {
+  std::mutex mu;
+  bool ready = false;
+  Slot slots[kSlots];
+  int next = 0;
+};
+
+constexpr int kMaxDevices = 16;
+DeviceState g_dev[kMaxDevices];
+
+int device_state(DeviceState** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HYDRO_EINVAL, "device %d out of range", dev);
+  DeviceState& st = g_dev[dev];
+  std::lock_guard<std::mutex> lk(st.mu);
+  if (!st.ready) {
+    for (int i = 0; i < kSlots; ++i) {
+      Slot& s = st.slots[i];
+      HIP_TRY(hipHostMalloc((void**)&s.host, sizeof(DevDesc) * kSlotCap, hipHostMallocDefault));
+      HIP_TRY(hipMalloc((void**)&s.dev, sizeof(DevDesc) * kSlotCap));
+      HIP_TRY(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+    }
+    st.ready = true;
+  }
+  *out = &st;
+  return HYDRO_OK;
+}
+
+int validate(const hydro_subgrid_t* sg, int32_t count, double dt, double dx) {
+  if (count < 0) return fail(HYDRO_EINVAL, "count %d < 0", count);
+  if (count > 0 && !sg) return fail(HYDRO_EINVAL, "sg is NULL");
+  if (!(dt >= 0.0) || !isfinite(dt)) return fail(HYDRO_EINVAL, "dt must be finite and >= 0");
+  if (!(dx > 0.0) || !isfinite(dx)) return fail(HYDRO_EINVAL, "dx must be finite and > 0");
+  for (int32_t i = 0; i < count; ++i) {
+    const hydro_subgrid_t& s = sg[i];
+    if (class_of(s.n, s.nfields) < 0)
+      return fail(HYDRO_EINVAL, "sub-grid %d: unsupported n=%d nfields=%d", i, s.n, s.nfields);
+    if (!s.u_in || !s.u_out) return fail(HYDRO_EINVAL, "sub-grid %d: NULL buffer", i);
+    if ((const void*)s.u_in == (const void*)s.u_out)
+      return fail(HYDRO_EINVAL, "sub-grid %d: u_out aliases u_in", i);
+    if (s.level < 0 || s.level > 30) return fail(HYDRO_EINVAL, "sub-grid %d: level %d", i, s.level);
+    if (s.reserved != 0) return fail(HYDRO_EINVAL, "sub-grid %d: reserved must be 0", i);
+  }
+  return HYDRO_OK;
+}
+
+template <int N, int F>
+int launch_table(const DevDesc* table, int n, double dt, double dx, double* amax,
+                 hipStream_t stream) {
+  if (n <= 0) return HYDRO_OK;
+  hipLaunchKernelGGL((hydro::hydro_table_kernel<N, F>), dim3(n),
+                     dim3(hydro::Shape<N>::kThreads), 0, stream, table, dt, dx, amax);
+  HIP_TRY(hipGetLastError());
+  return HYDRO_OK;
+}
+
+template <int N, int F>
+int launch_args(const ArgDescs& a, int n, double dt, double dx, double* amax,
+                hipStream_t stream) {
+  if (n <= 0) return HYDRO_OK;
+  hipLaunchKernelGGL((hydro::hydro_arg_kernel<N, F>), dim3(n),
+                     dim3(hydro::Shape<N>::kThreads), 0, stream, a, dt, dx, amax);
+  HIP_TRY(hipGetLastError());
+  return HYDRO_OK;
+}
+
+int dispatch_table(int cls, const DevDesc* table, int n, double dt, double dx,
+                   double* amax, hipStream_t s) {
+  switch (cls) {
+    case 0: return launch_table<8, 6>(table, n, dt, dx, amax, s);
+    case 1: return launch_table<8, 11>(table, n, dt, dx, amax, s);
+    case 2: return launch_table<12, 6>(table, n, dt, dx, amax, s);
+    case 3: return launch_table<12, 11>(table, n, dt, dx, amax, s);
+    case 4: return launch_table<16, 6>(table, n, dt, dx, amax, s);
+    case 5: return launch_table<16, 11>(table, n, dt, dx, amax, s);
+  }
+  return fail(HYDRO_EINVAL, "bad class");
+}
+
+int dispatch_args(int cls, const ArgDescs& a, int n, double dt, double dx,
+                  double* amax, hipStream_t s) {
+  switch (cls) {
+    case 0: return launch_args<8, 6>(a, n, dt, dx, amax, s);
+    case 1: return launch_args<8, 11>(a, n, dt, dx, amax, s);
+    case 2: return launch_args<12, 6>(a, n, dt, dx, amax, s);
+    case 3: return launch_args<12, 11>(a, n, dt, dx, amax, s);
+    case 4: return launch_args<16, 6>(a, n, dt, dx, amax, s);
+    case 5: return launch_args<16, 11>(a, n, dt, dx, amax, s);
+  }
+  return fail(HYDRO_EINVAL, "bad class");
+}
+
+
+const void* table_kernel_fn(int cls) {
+  switch (cls) {
+    case 0: return (const void*)hydro::hydro_table_kernel<8, 6>;
+    case 1: return (const void*)hydro::hydro_table_kernel<8, 11>;
+    case 2: return (const void*)hydro::hydro_table_kernel<12, 6>;
+    case 3: return (const void*)hydro::hydro_table_kernel<12, 11>;
+    case 4: return (const void*)hydro::hydro_table_kernel<16, 6>;
+    case 5: return (const void*)hydro::hydro_table_kernel<16, 11>;
+  }
+  return nullptr;
+}
+
+int threads_of_class(int cls) {
+  switch (cls / 2) {
+    case 0: return hydro::Shape<8>::kThreads;
+    case 1: return hydro::Shape<12>::kThreads;
+    default: return hydro::Shape<16>::kThreads;
+  }
+}
+
+DevDesc to_dev(const hydro_subgrid_t& s, int index) {
+  DevDesc d;
+  d.u_in = s.u_in;
+  d.u_out = s.u_out;
+  d.level = s.level;
+  d.index = index;
+  return d;
+}
+
+// One chunk of at most kSlotCap sub-grids starting at batch offset `base`.
+int step_chunk(DeviceState* st, const hydro_subgrid_t* sg, int count, int base,
+               double dt, double dx, double* amax, hipStream_t stream) {
+  int per_class[kClasses] = {0};
+  for (int i = 0; i < count; ++i) per_class[class_of(sg[i].n, sg[i].nfields)]++;
+  int need_table = 0;
+  for (int c = 0; c < kClasses; ++c)
+    if (per_class[c] > hydro::kArgDescs) need_table += per_class[c];
+
+  // Small classes: descriptors travel in the kernel arguments.
+  for (int c = 0; c < kClasses; ++c) {
+    if (per_class[c] == 0 || per_class[c] > hydro::kArgDescs) continue;
+    ArgDescs a;
+    memset(&a, 0, sizeof a);
+    int k = 0;
+    for (int i = 0; i < count; ++i)
+      if (class_of(sg[i].n, sg[i].nfields) == c) a.d[k++] = to_dev(sg[i], base + i);
+    int rc = dispatch_args(c, a, k, dt, dx, amax, stream);
+    if (rc) return rc;
+  }
+  if (need_table == 0) return HYDRO_OK;
+
+  Slot* slot;
+  {
+    std::lock_guard<std::mutex> lk(st->mu);
+    slot = &st->slots[st->next];
+    st->next = (st->next + 1) % kSlots;
+  }
+  if (slot->used) HIP_TRY(hipEventSynchronize(slot->done));
+  int off[kClasses];
+  int pos = 0;
+  for (int c = 0; c < kClasses; ++c) {
+    off[c] = pos;
+    if (per_class[c] > hydro::kArgDescs) pos += per_class[c];
+  }
+  int fill[kClasses];
+  memcpy(fill, off, sizeof fill);
+  for (int i = 0; i < count; ++i) {
+    int c = class_of(sg[i].n, sg[i].nfields);
+    if (per_class[c] > hydro::kArgDescs) slot->host[fill[c]++] = to_dev(sg[i], base + i);
+  }
+  HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, sizeof(DevDesc) * pos,
+                         hipMemcpyHostToDevice, stream));
+  for (int c = 0; c < kClasses; ++c) {
+    if (per_class[c] <= hydro::kArgDescs) continue;
+    int rc = dispatch_table(c, slot->dev + off[c], per_class[c], dt, dx, amax, stream);
+    if (rc) return rc;
+  }
+  HIP_TRY(hipEventRecord(slot->done, stream));
+  slot->used = true;
+  return HYDRO_OK;
+}
+
+}  // namespace
+
+// ---- plans ---------------------------------------------------------------
+struct hydro_plan {
+  int device = 0;
+  DevDesc* table = nullptr;  // device, classes contiguous
+  int count = 0;
+  int off[kClasses] = {0};
+  int num[kClasses] = {0};
+  // graph state
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t node[kClasses] = {nullptr};
+  struct Args {
+    const DevDesc* table;
+    double dt, dx;
+    double* amax;
+    void* ptrs[4];
+  } args[kClasses];
+};
+
+namespace {
+
+void plan_set_args(hydro_plan* p, int c, double dt, double dx, double* amax) {
+  auto& a = p->args[c];
+  a.table = p->table + p->off[c];
+  a.dt = dt;
+  a.dx = dx;
+  a.amax = amax;
+  a.ptrs[0] = &a.table;
+  a.ptrs[1] = &a.dt;
+  a.ptrs[2] = &a.dx;
+  a.ptrs[3] = &a.amax;
+}
+
+hipKernelNodeParams plan_node_params(hydro_plan* p, int c) {
+  hipKernelNodeParams kp;
+  memset(&kp, 0, sizeof kp);
+  kp.func = const_cast<void*>(table_kernel_fn(c));
+  kp.gridDim = dim3(p->num[c]);
+  kp.blockDim = dim3(threads_of_class(c));
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = p->args[c].ptrs;
+  kp.extra = nullptr;
+  return kp;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hydro_step(const hydro_subgrid_t* sg, int32_t count, double dt, double dx,
+               double* amax_dev, void* stream) {
+  g_err[0] = '\0';
+  int rc = validate(sg, count, dt, dx);
+  if (rc) return rc;
+  if (count == 0) return HYDRO_OK;
+  DeviceState* st;
+  rc = device_state(&st);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  for (int base = 0; base < count; base += kSlotCap) {
+    int n = count - base < kSlotCap ? count - base : kSlotCap;
+    rc = step_chunk(st, sg + base, n, base, dt, dx, amax_dev, s);
+    if (rc) return rc;
+  }
+  return HYDRO_OK;
+}
+
+int hydro_step_each(const hydro_subgrid_t* sg, int32_t count, double dt,
+                    double dx, double* amax_dev, void* stream) {
+  g_err[0] = '\0';
+  int rc = validate(sg, count, dt, dx);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < count; ++i) {
+    ArgDescs a;
+    memset(&a, 0, sizeof a);
+    a.d[0] = to_dev(sg[i], i);
+    rc = dispatch_args(class_of(sg[i].n, sg[i].nfields), a, 1, dt, dx, amax_dev, s);
+    if (rc) return rc;
+  }
+  return HYDRO_OK;
+}
+
+
+int hydro_plan_create(hydro_plan_t** out, const hydro_subgrid_t* sg, int32_t count) {
+  g_err[0] = '\0';
+  if (!out) return fail(HYDRO_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(sg, count, 0.0, 1.0);
+  if (rc) return rc;
+  hydro_plan* p = new hydro_plan();
+  HIP_TRY(hipGetDevice(&p->device));
+  p->count = count;
+  std::vector<DevDesc> host((size_t)(count > 0 ? count : 1));
+  for (int i = 0; i < count; ++i) p->num[class_of(sg[i].n, sg[i].nfields)]++;
+  int pos = 0;
+  for (int c = 0; c < kClasses; ++c) {
+    p->off[c] = pos;
+    pos += p->num[c];
+  }
+  int fill[kClasses];
+  memcpy(fill, p->off, sizeof fill);
+  for (int i = 0; i < count; ++i) host[fill[class_of(sg[i].n, sg[i].nfields)]++] = to_dev(sg[i], i);
+  if (count > 0) {
+    hipError_t e = hipMalloc((void**)&p->table, sizeof(DevDesc) * count);
+    if (e != hipSuccess) {
+      delete p;
+      return fail(HYDRO_EHIP, "hipMalloc(plan table): %s", hipGetErrorString(e));
+    }
+    e = hipMemcpy(p->table, host.data(), sizeof(DevDesc) * count, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(p->table);
+      delete p;
+      return fail(HYDRO_EHIP, "hipMemcpy(plan table): %s", hipGetErrorString(e));
+    }
+  }
+  *out = p;
+  return HYDRO_OK;
+}
+
+int hydro_plan_step(hydro_plan_t* p, double dt, double dx, double* amax_dev, void* stream) {
+  g_err[0] = '\0';
+  if (!p) return fail(HYDRO_EINVAL, "plan is NULL");
+  int rc = validate(nullptr, 0, dt, dx);
+  if (rc) return rc;
+  for (int c = 0; c < kClasses; ++c) {
+    if (!p->num[c]) continue;
+    rc = dispatch_table(c, p->table + p->off[c], p->num[c], dt, dx, amax_dev, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return HYDRO_OK;
+}
+
+int hydro_plan_launch_graph(hydro_plan_t* p, double dt, double dx, double* amax_dev, void* stream) {
+  g_err[0] = '\0';
+  if (!p) return fail(HYDRO_EINVAL, "plan is NULL");
+  int rc = validate(nullptr, 0, dt, dx);
+  if (rc) return rc;
+  if (p->count == 0) return HYDRO_OK;
+  if (!p->exec) {
+    HIP_TRY(hipGraphCreate(&p->graph, 0));
+    for (int c = 0; c < kClasses; ++c) {
+      if (!p->num[c]) continue;
+      plan_set_args(p, c, dt, dx, amax_dev);
+      hipKernelNodeParams kp = plan_node_params(p, c);
+      HIP_TRY(hipGraphAddKernelNode(&p->node[c], p->graph, nullptr, 0, &kp));
+    }
+    HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+  } else {
+    for (int c = 0; c < kClasses; ++c) {
+      if (!p->num[c]) continue;
+      auto& a = p->args[c];
+      if (a.dt == dt && a.dx == dx && a.amax == amax_dev) continue;
+      plan_set_args(p, c, dt, dx, amax_dev);
+      hipKernelNodeParams kp = plan_node_params(p, c);
+      HIP_TRY(hipGraphExecKernelNodeSetParams(p->exec, p->node[c], &kp));
+    }
+  }
+  HIP_TRY(hipGraphLaunch(p->exec, (hipStream_t)stream));
+  return HYDRO_OK;
+}
+
+int hydro_plan_destroy(hydro_plan_t* p) {
+  g_err[0] = '\0';
+  if (!p) return HYDRO_OK;
+  int rc = HYDRO_OK;
+  if (hipDeviceSynchronize() != hipSuccess) rc = fail(HYDRO_EHIP, "hipDeviceSynchronize failed");
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->table) (void)hipFree(p->table);
+  delete p;
+  return rc;
+}
+
+const char* hydro_last_error(void) { return g_err; }
+
+const char* hydro_version(void) { return "hydroagg v1 line-march gfx950"; }
+
+}  // extern "C"

@@ -1,0 +1,176 @@
+"""Parity of the HIP path with the CPU oracle on the same seeded inputs.
+
+Bar: per field, max |U_gpu - U_oracle| / max |U_oracle| <= 1e-12 over all
+interior cells (FP64 step; the two sides differ only in rounding order);
+amax relative error <= 1e-13.  Bitwise where the mathematics fixes the value
+(uniform state, dt = 0, power-of-two scaling, batch independence)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2210_06438_amd import hydroagg, workloads
+from tests.gpu_util import ghost_mask, interior, normwise
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+ATOL_AMAX = 1e-13
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def run_gpu(U, dt, dx, levels=None, each=False, dev="cuda:0"):
+    """Step a [count, F, M, M, M] batch on the GPU; returns (u_out, amax)."""
+    u_in = torch.from_numpy(np.ascontiguousarray(U)).to(dev)
+    u_out = u_in.clone()
+    amax = torch.zeros(U.shape[0], dtype=torch.float64, device=dev)
+    descs = hydroagg.subgrids(u_in, u_out, levels=levels)
+    (hydroagg.hydro_step_each if each else hydroagg.hydro_step)(descs, dt, dx, amax)
+    torch.cuda.synchronize()
+    return u_out.cpu().numpy(), amax.cpu().numpy()
+
+
+def check(U, dt, dx, oracle_mod, levels=None, each=False):
+    n = U.shape[2] - 6
+    print(f"parity: count={U.shape[0]} n={n} F={U.shape[1]} dt={dt:.3e}", flush=True)
+    ref, ref_amax = oracle_mod.step(U, dt, dx, levels=levels)
+    got, amax = run_gpu(U, dt, dx, levels=levels, each=each)
+    err = normwise(interior(got, n), interior(ref, n))
+    assert np.all(err <= TOL), err
+    rel = np.max(np.abs(amax - ref_amax) / ref_amax)
+    assert rel <= ATOL_AMAX, rel
+    g = ghost_mask(n)
+    assert np.array_equal(got[:, :, g], U[:, :, g]), "ghost cells of u_out were written"
+    return got, amax
+
+
+def courant_dt(oracle_mod, U, dx, levels=None, cfl=0.4):
+    _, a = oracle_mod.step(U, 0.0, dx, levels=levels)
+    lv = np.zeros(len(a)) if levels is None else np.asarray(levels)
+    return cfl * float(np.min(dx * 2.0 ** (-lv) / a))
+
+
+def test_brick_c1(dev, oracle_mod):
+    U = workloads.brick(seed=1)
+    dx = 1 / 64
+    check(U, courant_dt(oracle_mod, U, dx), dx, oracle_mod)
+
+
+@pytest.mark.parametrize("n", [8, 12, 16])
+@pytest.mark.parametrize("nf", [6, 11])
+def test_random_smooth(dev, oracle_mod, n, nf):
+    U = workloads.random_smooth(12, n=n, nfields=nf, seed=100 + n + nf)
+    dx = 0.05
+    check(U, courant_dt(oracle_mod, U, dx), dx, oracle_mod)
+
+
+def test_small_batches_use_kernel_arguments(dev, oracle_mod):
+    for count in (1, 3, 8, 9):
+        U = workloads.random_smooth(count, n=8, nfields=11, seed=200 + count)
+        check(U, 0.002, 0.05, oracle_mod)
+
+
+def test_per_subgrid_launch_matches(dev, oracle_mod):
+    U = workloads.random_smooth(10, n=12, nfields=11, seed=300)
+    check(U, 0.002, 0.05, oracle_mod, each=True)
+
+
+def test_polytrope_mix_with_levels(dev, oracle_mod):
+    groups = workloads.polytrope(count=40, seed=3)
+    for N, levels, U, _ in groups:
+        dx = 0.5
+        dt = courant_dt(oracle_mod, U, dx, levels=levels)
+        check(U, dt, dx, oracle_mod, levels=levels)
+
+
+def test_uniform_state_bitwise(dev):
+    for n, nf in ((8, 6), (12, 11), (16, 11)):
+        M = n + 6
+        W = [1.3, 0.2, -0.4, 0.7, 2.1] + [0.3] * (nf - 5)
+        e = W[4] / (5 / 3 - 1) + 0.5 * W[0] * (W[1] ** 2 + W[2] ** 2 + W[3] ** 2)
+        Uc = np.array([W[0], W[0] * W[1], W[0] * W[2], W[0] * W[3], e] + W[5:])
+        U = np.broadcast_to(Uc[None, :, None, None, None], (3, nf, M, M, M)).copy()
+        got, amax = run_gpu(U, 0.01, 0.02)
+        assert np.array_equal(got, U)
+        c = math.sqrt(5 / 3 * 2.1 / 1.3)
+        assert np.allclose(amax, 0.7 + c, rtol=1e-14, atol=0)
+
+
+def test_dt_zero_and_scaling_bitwise(dev):
+    U = workloads.random_smooth(6, n=8, nfields=11, seed=400)
+    got0, _ = run_gpu(U, 0.0, 0.05)
+    assert np.array_equal(got0, U)
+    a, am = run_gpu(U, 0.003, 0.05, levels=[0, 1, 2, 0, 1, 2])
+    b, bm = run_gpu(2.0 * U, 0.003, 0.05, levels=[0, 1, 2, 0, 1, 2])
+    assert np.array_equal(interior(b, 8), 2.0 * interior(a, 8))
+    assert np.array_equal(am, bm)
+    c, cm = run_gpu(U, 0.006, 0.1, levels=[0, 1, 2, 0, 1, 2])
+    assert np.array_equal(interior(c, 8), interior(a, 8)) and np.array_equal(cm, am)
+
+
+def test_brick_conservation_on_gpu(dev):
+    U = workloads.brick(seed=5)
+    got, amax = run_gpu(U, 0.0, 1 / 64)
+    dt = 0.4 / 64 / amax.max()
+    got, _ = run_gpu(U, dt, 1 / 64)
+    for f in range(U.shape[1]):
+        before = math.fsum(interior(U, 8)[:, f].ravel())
+        after = math.fsum(interior(got, 8)[:, f].ravel())
+        scale = math.fsum(np.abs(interior(U, 8)[:, f]).ravel())
+        assert abs(after - before) <= 1e-13 * scale
+
+
+def test_batch_independence_bitwise(dev):
+    """A sub-grid's result does not depend on the batch it runs in."""
+    U8 = workloads.random_smooth(20, n=8, nfields=11, seed=500)
+    U12 = workloads.random_smooth(5, n=12, nfields=11, seed=501)
+    dt, dx = 0.002, 0.05
+    alone = [run_gpu(U8[i:i + 1], dt, dx)[0][0] for i in (0, 7, 19)]
+    batch, _ = run_gpu(U8, dt, dx)
+    each, _ = run_gpu(U8, dt, dx, each=True)
+    perm = np.random.default_rng(0).permutation(20)
+    shuffled, _ = run_gpu(U8[perm], dt, dx)
+    for k, i in enumerate((0, 7, 19)):
+        assert np.array_equal(batch[i], alone[k])
+    assert np.array_equal(batch, each)
+    assert np.array_equal(shuffled, batch[perm])
+    # mixed shapes in one call
+    u8 = torch.from_numpy(U8).to(dev)
+    u12 = torch.from_numpy(U12).to(dev)
+    o8, o12 = u8.clone(), u12.clone()
+    d = hydroagg.concat(hydroagg.subgrids(u12, o12), hydroagg.subgrids(u8, o8))
+    hydroagg.hydro_step(d, dt, dx)
+    torch.cuda.synchronize()
+    assert np.array_equal(o8.cpu().numpy(), batch)
+    ref12, _ = run_gpu(U12, dt, dx)
+    assert np.array_equal(o12.cpu().numpy(), ref12)
+
+
+def test_full_size_batch_sampled(dev, oracle_mod):
+    """4096 sub-grids of 8^3 with 11 fields (the batching workload) in one
+    aggregated call; a sample of sub-grids is checked against the oracle."""
+    count = 4096
+    print("full-size: generating 4096 x 8^3 x 11 fields", flush=True)
+    U = workloads.random_smooth(count, n=8, nfields=11, seed=2)
+    u_in = torch.from_numpy(U).to(dev)
+    u_out = u_in.clone()
+    amax = torch.zeros(count, dtype=torch.float64, device=dev)
+    d = hydroagg.subgrids(u_in, u_out)
+    hydroagg.hydro_step(d, 0.0, 1 / 64, amax)
+    torch.cuda.synchronize()
+    dt = 0.4 / 64 / float(amax.max())
+    hydroagg.hydro_step(d, dt, 1 / 64, amax)
+    torch.cuda.synchronize()
+    sample = np.unique(np.r_[0, count - 1, np.random.default_rng(1).integers(0, count, 14)])
+    got = u_out[torch.from_numpy(sample).to(dev)].cpu().numpy()
+    ref, ref_amax = oracle_mod.step(U[sample], dt, 1 / 64)
+    assert np.all(normwise(interior(got, 8), interior(ref, 8)) <= TOL)
+    a = amax.cpu().numpy()[sample]
+    assert np.max(np.abs(a - ref_amax) / ref_amax) <= ATOL_AMAX
