@@ -15,6 +15,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -42,6 +43,20 @@ def bytes_per_subgrid(n, nf):
     return floor, tile
 
 
+def measured_traffic(version, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter record, or
+    None when that record was taken on another build of the kernel."""
+    path = os.path.join(ROOT, "paper_2210_06438_amd", "measured_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_version") != version or rec.get("workload") != workload:
+        return None
+    return int(rec["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,6 +68,10 @@ def main():
     ap.add_argument("--each-reps", type=int, default=3,
                     help="timed repetitions of the one-launch-per-sub-grid baseline")
     ap.add_argument("--cpu-reps", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum wall time of the oracle measurement")
+    ap.add_argument("--copy-reps", type=int, default=10,
+                    help="timed repetitions of a plain device copy of the input buffer")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads (0 = OMP_NUM_THREADS or all cores)")
@@ -89,7 +108,7 @@ def main():
     plan.step(0.0, dx, amax, stream)
     torch.cuda.synchronize()
     dt = 0.4 * dx / float(amax.max())
-    log(f"dt = {dt:.6e}")
+    log(f"dt = {dt:.6e}; library {hydroagg.version()}")
 
     # ---- aggregated: one hipGraph launch per step -------------------------
     for _ in range(args.warmup):
@@ -120,20 +139,39 @@ def main():
         each_ms = e0.elapsed_time(e1) / args.each_reps
         log(f"per-sub-grid launches: {each_ms:.2f} ms/step")
 
+    # ---- a plain device copy of the same buffer: measured bandwidth reference
+    copy_gbs = None
+    if args.copy_reps > 0:
+        u_out.copy_(u_in)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.copy_reps):
+            u_out.copy_(u_in)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        copy_ms = e0.elapsed_time(e1) / args.copy_reps
+        copy_gbs = 2 * u_in.numel() * 8 / (copy_ms * 1e-3) / 1e9
+        log(f"device copy of {u_in.numel() * 8 / 1e9:.2f} GB: {copy_ms * 1e3:.1f} us, {copy_gbs:.0f} GB/s")
+
     floor_b, tile_b = bytes_per_subgrid(n, nf)
-    achieved = floor_b * count / (ms * 1e-3) / 1e9
-    achieved_tile = tile_b * count / (ms * 1e-3) / 1e9
+    achieved = tile_b * count / (ms * 1e-3) / 1e9
+    achieved_floor = floor_b * count / (ms * 1e-3) / 1e9
+    version = hydroagg.version()
+    workload_name = f"{count}x{n}^3 F={nf}"
     roofline = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
-        "kernel": f"hydro_table_kernel<{n},{nf}>",
-        "bytes_per_launch": floor_b * count,
-        "achieved_tile_bytes": round(achieved_tile, 1),
-        "frac_tile_bytes": round(achieved_tile / HBM_PEAK_GBS, 4),
+        "traffic": measured_traffic(version, workload_name),
+        "kernel": (f"hydro_lds8_kernel<{nf}>" if n == 8 else f"hydro_table_kernel<{n},{nf}>"),
+        "kernel_version": version,
+        "algorithmic_bytes_per_launch": tile_b * count,
+        "bytes_definition": "stored (n+6)^3 tile read once + interior n^3 written once, 8 B x F per cell",
+        "achieved_floor_gbs": round(achieved_floor, 1),
+        "floor_bytes_per_launch": floor_b * count,
+        "measured_copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
     }
 
     cpu = None
@@ -141,18 +179,21 @@ def main():
         import oracle
         threads = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS", "0") or 0) \
             or os.cpu_count() or 1
-        log(f"cpu baseline: oracle on the full batch, {threads} threads")
-        best = None
-        for _ in range(max(args.cpu_reps, 1)):
+        log(f"cpu baseline: oracle on the full batch, {threads} threads, "
+            f">= {args.cpu_seconds:.0f} s")
+        times = []
+        t_all = time.time()
+        while len(times) < max(args.cpu_reps, 1) or time.time() - t_all < args.cpu_seconds:
             t0 = time.time()
             oracle.step(U, dt, dx, nthreads=threads)
-            el = time.time() - t0
-            best = el if best is None else min(best, el)
-        cpu = {"value": round(cells / best, 1), "unit": "cell-updates/s", "cores": threads,
+            times.append(time.time() - t0)
+        med = statistics.median(times)
+        cpu = {"value": round(cells / med, 1), "unit": "cell-updates/s", "cores": threads,
                "kind": "oracle",
-               "sample": f"the full {count}-sub-grid workload, best of {max(args.cpu_reps, 1)} "
-                         f"runs ({best:.2f} s each), OpenMP over sub-grids"}
-        log(f"cpu baseline {cells / best / 1e6:.2f} M cell-updates/s")
+               "sample": f"the full {count}-sub-grid workload stepped {len(times)} times "
+                         f"({sum(times):.1f} s wall, median {med:.3f} s per step), "
+                         "OpenMP over sub-grids"}
+        log(f"cpu baseline {cells / med / 1e6:.2f} M cell-updates/s")
 
     out = {
         "metric": METRIC,

@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import glob
+import hashlib
 import os
 import subprocess
 
@@ -17,14 +18,31 @@ FLAGS = [
 ]
 
 
+def source_files():
+    return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")) +
+                  glob.glob(os.path.join(HERE, "csrc", "*.hpp")) +
+                  glob.glob(os.path.join(HERE, "csrc", "*.cpp")) +
+                  [os.path.join(os.path.dirname(HERE), "include", "hydroagg.h")])
+
+
+def source_hash() -> str:
+    """Short hash of every source the library is built from; the library
+    reports it through hydro_version() so measurements can be tied to the
+    exact kernel they were taken on."""
+    h = hashlib.sha1()
+    for f in source_files():
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
 def build(verbose: bool = False) -> str:
-    deps = SOURCES + glob.glob(os.path.join(HERE, "csrc", "*.hpp")) + \
-        [os.path.join(os.path.dirname(HERE), "include", "hydroagg.h")]
-    for d in deps:
+    for d in SOURCES:
         if not os.path.exists(d):
             raise FileNotFoundError(d)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *SOURCES, "-o", tmp]
+    cmd = [HIPCC, *FLAGS, f'-DHYDRO_SRC_HASH="{source_hash()}"', *SOURCES, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

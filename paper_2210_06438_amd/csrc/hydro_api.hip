@@ -20,6 +20,7 @@
 
 #include "../../include/hydroagg.h"
 #include "hydro_kernel.hpp"
+#include "hydro_lds8.hpp"
 
 using hydro::ArgDescs;
 using hydro::DevDesc;
@@ -106,6 +107,8 @@ int validate(const hydro_subgrid_t* sg, int32_t count, double dt, double dx) {
     if (!s.u_in || !s.u_out) return fail(HYDRO_EINVAL, "sub-grid %d: NULL buffer", i);
     if ((const void*)s.u_in == (const void*)s.u_out)
       return fail(HYDRO_EINVAL, "sub-grid %d: u_out aliases u_in", i);
+    if (((uintptr_t)s.u_in | (uintptr_t)s.u_out) & 15)
+      return fail(HYDRO_EINVAL, "sub-grid %d: buffers must be 16-byte aligned", i);
     if (s.level < 0 || s.level > 30) return fail(HYDRO_EINVAL, "sub-grid %d: level %d", i, s.level);
     if (s.reserved != 0) return fail(HYDRO_EINVAL, "sub-grid %d: reserved must be 0", i);
   }
@@ -116,8 +119,12 @@ template <int N, int F>
 int launch_table(const DevDesc* table, int n, double dt, double dx, double* amax,
                  hipStream_t stream) {
   if (n <= 0) return HYDRO_OK;
-  hipLaunchKernelGGL((hydro::hydro_table_kernel<N, F>), dim3(n),
-                     dim3(hydro::Shape<N>::kThreads), 0, stream, table, dt, dx, amax);
+  if constexpr (N == 8)
+    hipLaunchKernelGGL((hydro::hydro_lds8_kernel<F>), dim3(n),
+                       dim3(hydro::Lds8::kThreads), 0, stream, table, dt, dx, amax);
+  else
+    hipLaunchKernelGGL((hydro::hydro_table_kernel<N, F>), dim3(n),
+                       dim3(hydro::Shape<N>::kThreads), 0, stream, table, dt, dx, amax);
   HIP_TRY(hipGetLastError());
   return HYDRO_OK;
 }
@@ -126,8 +133,12 @@ template <int N, int F>
 int launch_args(const ArgDescs& a, int n, double dt, double dx, double* amax,
                 hipStream_t stream) {
   if (n <= 0) return HYDRO_OK;
-  hipLaunchKernelGGL((hydro::hydro_arg_kernel<N, F>), dim3(n),
-                     dim3(hydro::Shape<N>::kThreads), 0, stream, a, dt, dx, amax);
+  if constexpr (N == 8)
+    hipLaunchKernelGGL((hydro::hydro_lds8_arg_kernel<F>), dim3(n),
+                       dim3(hydro::Lds8::kThreads), 0, stream, a, dt, dx, amax);
+  else
+    hipLaunchKernelGGL((hydro::hydro_arg_kernel<N, F>), dim3(n),
+                       dim3(hydro::Shape<N>::kThreads), 0, stream, a, dt, dx, amax);
   HIP_TRY(hipGetLastError());
   return HYDRO_OK;
 }
@@ -161,8 +172,8 @@ int dispatch_args(int cls, const ArgDescs& a, int n, double dt, double dx,
 
 const void* table_kernel_fn(int cls) {
   switch (cls) {
-    case 0: return (const void*)hydro::hydro_table_kernel<8, 6>;
-    case 1: return (const void*)hydro::hydro_table_kernel<8, 11>;
+    case 0: return (const void*)hydro::hydro_lds8_kernel<6>;
+    case 1: return (const void*)hydro::hydro_lds8_kernel<11>;
     case 2: return (const void*)hydro::hydro_table_kernel<12, 6>;
     case 3: return (const void*)hydro::hydro_table_kernel<12, 11>;
     case 4: return (const void*)hydro::hydro_table_kernel<16, 6>;
@@ -173,7 +184,7 @@ const void* table_kernel_fn(int cls) {
 
 int threads_of_class(int cls) {
   switch (cls / 2) {
-    case 0: return hydro::Shape<8>::kThreads;
+    case 0: return hydro::Lds8::kThreads;
     case 1: return hydro::Shape<12>::kThreads;
     default: return hydro::Shape<16>::kThreads;
   }
@@ -419,6 +430,9 @@ int hydro_plan_destroy(hydro_plan_t* p) {
 
 const char* hydro_last_error(void) { return g_err; }
 
-const char* hydro_version(void) { return "hydroagg v1 line-march gfx950"; }
+#ifndef HYDRO_SRC_HASH
+#define HYDRO_SRC_HASH "unknown"
+#endif
+const char* hydro_version(void) { return "hydroagg gfx950 src " HYDRO_SRC_HASH; }
 
 }  // extern "C"

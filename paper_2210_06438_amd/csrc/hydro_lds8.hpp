@@ -1,0 +1,390 @@
+// hydro_lds8.hpp -- gfx950 kernel for 8^3 sub-grids: each input byte read
+// from HBM once, direction sums kept on chip.
+//
+// One work-group of 192 lanes steps one sub-grid: wave 0 owns the 64 lines
+// along x, wave 1 the lines along y, wave 2 the lines along z (one lane per
+// line of 14 cells whose transverse coordinates are interior).  Every stored
+// value the face-centred stencil needs is read from HBM exactly once: the
+// interior cells (needed by all three directions) are loaded cooperatively
+// with coalesced loads into LDS; the six ghost cells of a line (needed by that
+// line only) are loaded by its lane straight into registers.  The 36 rows
+// that lie in both a y- and a z-ghost layer, and all edge/corner ghosts, are
+// never read.
+//
+// Hydro core (rho, s, E): once the five lines are in registers, the lane
+// marches them (primitive recovery -> limited slopes -> interface offsets ->
+// parabola constraint -> central-upwind flux).  It keeps, for every face of
+// its line, the two weights w- and w+ of the expanded central-upwind flux
+// (paper Section IV-B; Kurganov-Noelle-Petrova), with which the flux of any
+// passively advected density q is w- q(W-) + w+ q(W+).  Passive fields (tau,
+// species) are then staged and marched one at a time with those weights.
+//
+// Direction sums: lanes of the x and y waves add their flux differences into
+// a zeroed LDS accumulator with atomic adds -- exactly two adds onto zero per
+// cell, which is order-independent, so the result is deterministic.  Lanes of
+// the z wave keep U - lambda*dF_z of their column (in LDS for the hydro core,
+// in registers for a passive field) and, after a barrier, write
+// U_out = (U - lambda*dF_z) - lambda*(dF_x + dF_y).
+#pragma once
+
+#include "hydro_kernel.hpp"
+
+namespace hydro {
+
+struct Lds8 {
+  static constexpr int N = 8;
+  static constexpr int M = 14;
+  static constexpr int RS = 9;     // LDS row stride of a cell array (doubles)
+  static constexpr int PS = 81;    // LDS plane stride
+  static constexpr int P = N * PS; // one field of a cell array: 648 doubles
+  static constexpr int kThreads = 192;
+  static constexpr long FS = (long)M * M * M;
+};
+
+// LDS index of interior cell (x, y, z), 0 <= x, y, z < 8.
+__device__ __forceinline__ int lcell(int x, int y, int z) {
+  return z * Lds8::PS + y * Lds8::RS + x;
+}
+
+// Sliding-window PPM reconstruction of K components along a line, in offset
+// form (see hydro_kernel.hpp).  step<STAGE>() consumes q_i; from stage 5 on it
+// returns the face states W-, W+ of the face (i-3)+1/2.
+template <int K>
+struct Recon {
+  double q1[K], q2[K], h2[K], dLp[K], qRp[K];
+
+  template <int STAGE>
+  __device__ __forceinline__ void step(const double (&q)[K], double (&Wm)[K],
+                                       double (&Wp)[K]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if constexpr (STAGE == 0) {
+        q1[k] = q[k];
+        continue;
+      }
+      if constexpr (STAGE == 1) {
+        q2[k] = q1[k];
+        q1[k] = q[k];
+        continue;
+      }
+      const double d1 = q1[k] - q2[k];  // q_{i-1} - q_{i-2}
+      const double dn = q[k] - q1[k];   // q_i - q_{i-1}
+      const double h = half_slope(d1, dn);
+      if constexpr (STAGE == 2) {
+        h2[k] = h;
+        q2[k] = q1[k];
+        q1[k] = q[k];
+        continue;
+      }
+      const double e = 0.5 * d1 - (h - h2[k]) * (1.0 / 3.0);
+      if constexpr (STAGE >= 4) {
+        double oL, oR;
+        limit_edges(dLp[k], e, oL, oR);
+        if constexpr (STAGE >= 5) {
+          Wm[k] = qRp[k];
+          Wp[k] = q2[k] - oL;
+        }
+        qRp[k] = q2[k] + oR;
+      }
+      dLp[k] = d1 - e;
+      h2[k] = h;
+      q2[k] = q1[k];
+      q1[k] = q[k];
+    }
+  }
+};
+
+// Central-upwind flux of the hydro core (fields in x, y, z order) through a
+// face normal to the axis selected by the 0/1 masks (ex, ey, ez).  W = (rho,
+// vx, vy, vz, p).  Returns max(a+, -a-); writes F[5] and the weights.
+__device__ __forceinline__ double core_flux(const double (&Wm)[5],
+                                            const double (&Wp)[5], double ex,
+                                            double ey, double ez,
+                                            double (&Fh)[5], double& wm,
+                                            double& wp) {
+  const double vnm = ex * Wm[1] + ey * Wm[2] + ez * Wm[3];
+  const double vnp = ex * Wp[1] + ey * Wp[2] + ez * Wp[3];
+  const double cm = sqrt(kGamma * Wm[4] / Wm[0]);
+  const double cp = sqrt(kGamma * Wp[4] / Wp[0]);
+  const double ap = fmax(fmax(vnm + cm, vnp + cp), 0.0);
+  const double am = fmin(fmin(vnm - cm, vnp - cp), 0.0);
+  const double inv = 1.0 / (ap - am);
+  wm = ap * (vnm - am) * inv;
+  wp = am * (ap - vnp) * inv;
+  const double Em = Wm[4] / kGm1 +
+                    0.5 * Wm[0] * (Wm[1] * Wm[1] + Wm[2] * Wm[2] + Wm[3] * Wm[3]);
+  const double Ep = Wp[4] / kGm1 +
+                    0.5 * Wp[0] * (Wp[1] * Wp[1] + Wp[2] * Wp[2] + Wp[3] * Wp[3]);
+  const double pt = (ap * Wm[4] - am * Wp[4]) * inv;
+  Fh[0] = wm * Wm[0] + wp * Wp[0];
+  Fh[1] = wm * (Wm[0] * Wm[1]) + wp * (Wp[0] * Wp[1]) + ex * pt;
+  Fh[2] = wm * (Wm[0] * Wm[2]) + wp * (Wp[0] * Wp[2]) + ey * pt;
+  Fh[3] = wm * (Wm[0] * Wm[3]) + wp * (Wp[0] * Wp[3]) + ez * pt;
+  Fh[4] = wm * Em + wp * Ep + (ap * (Wm[4] * vnm) - am * (Wp[4] * vnp)) * inv;
+  return fmax(ap, -am);
+}
+
+__device__ __forceinline__ void to_prim(const double (&U)[5], double (&q)[5]) {
+  const double r = 1.0 / U[0];
+  const double vx = U[1] * r, vy = U[2] * r, vz = U[3] * r;
+  q[0] = U[0];
+  q[1] = vx;
+  q[2] = vy;
+  q[3] = vz;
+  q[4] = kGm1 * (U[4] - 0.5 * (U[1] * vx + U[2] * vy + U[3] * vz));
+}
+
+// Stored index (within one field) of line position i for lane (a, b) of the
+// wave that owns direction dir.
+__device__ __forceinline__ int gline(int dir, int a, int b, int i) {
+  constexpr int M = Lds8::M;
+  if (dir == 0) return ((b + kGhost) * M + (a + kGhost)) * M + i;
+  if (dir == 1) return ((b + kGhost) * M + i) * M + (a + kGhost);
+  return (i * M + (b + kGhost)) * M + (a + kGhost);
+}
+
+// This lane's share of the interior of `nf` consecutive fields starting at
+// `src`: element j of the share is interior cell t + j*192 of the fields
+// stacked [f][z][y][x].
+template <int NF>
+struct Share {
+  static constexpr int K = (NF * 512 + Lds8::kThreads - 1) / Lds8::kThreads;
+  double v[K];
+};
+
+template <int NF>
+__device__ __forceinline__ void load_share(const double* __restrict__ src, int t,
+                                           Share<NF>& sh) {
+#pragma unroll
+  for (int j = 0; j < Share<NF>::K; ++j) {
+    const int e = t + j * Lds8::kThreads;
+    if (e < NF * 512) {
+      const int f = e >> 9, x = e & 7, y = (e >> 3) & 7, z = (e >> 6) & 7;
+      sh.v[j] = src[f * Lds8::FS + ((z + kGhost) * Lds8::M + (y + kGhost)) * Lds8::M +
+                    (x + kGhost)];
+    }
+  }
+}
+
+template <int NF>
+__device__ __forceinline__ void store_share(double* lds, int t, const Share<NF>& sh) {
+#pragma unroll
+  for (int j = 0; j < Share<NF>::K; ++j) {
+    const int e = t + j * Lds8::kThreads;
+    if (e < NF * 512) {
+      const int f = e >> 9, x = e & 7, y = (e >> 3) & 7, z = (e >> 6) & 7;
+      lds[f * Lds8::P + lcell(x, y, z)] = sh.v[j];
+    }
+  }
+}
+
+// The six ghost positions (0, 1, 2, 11, 12, 13) of this lane's line for NF
+// consecutive fields.
+template <int NF>
+__device__ __forceinline__ void load_ghosts(const double* __restrict__ src, int dir,
+                                            int a, int b, double (&g)[NF][6]) {
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int i = j < 3 ? j : j + 8;
+      g[f][j] = src[f * Lds8::FS + gline(dir, a, b, i)];
+    }
+  }
+}
+
+template <int STAGE, int K>
+__device__ __forceinline__ void recon_step(Recon<K>& rc, const double (&q)[K],
+                                           double (&Wm)[K], double (&Wp)[K]) {
+  rc.template step<STAGE>(q, Wm, Wp);
+}
+
+template <int I, int K>
+__device__ __forceinline__ void recon_at(Recon<K>& rc, const double (&q)[K],
+                                         double (&Wm)[K], double (&Wp)[K]) {
+  recon_step<(I < 6 ? I : 6), K>(rc, q, Wm, Wp);
+}
+
+template <int F>
+__device__ __forceinline__ void lds8_step(const DevDesc& d, double dt, double dx,
+                                          double* __restrict__ amax_out) {
+  constexpr int M = Lds8::M;
+  constexpr int N = Lds8::N;
+  constexpr long FS = Lds8::FS;
+  constexpr int P = Lds8::P;
+  constexpr int NP = F - 5;  // passive fields
+  // tin: interior of the staged fields.  acc: x+y flux differences (two
+  // atomic adds onto zero per cell).  held: the z lanes' U - lambda*dF_z of
+  // the hydro core.
+  __shared__ double tin[5 * P];
+  __shared__ double acc[5 * P];
+  __shared__ double held[5 * P];
+  __shared__ double red[3];
+
+  const int t = threadIdx.x;
+  const int dir = t >> 6;          // wave-uniform
+  const int l = t & 63;
+  const int a = l & 7, b = l >> 3;
+  const double lambda = dt / ldexp(dx, -d.level);
+  const double ex = dir == 0 ? 1.0 : 0.0;
+  const double ey = dir == 1 ? 1.0 : 0.0;
+  const double ez = dir == 2 ? 1.0 : 0.0;
+  // interior line position c (3..10) -> LDS cell lbase + (c - 3) * lstride
+  const int lbase = dir == 0 ? lcell(0, a, b) : dir == 1 ? lcell(a, 0, b) : lcell(a, b, 0);
+  const int lstride = dir == 0 ? 1 : dir == 1 ? Lds8::RS : Lds8::PS;
+
+  // ---- stage the hydro core -------------------------------------------------
+  Share<5> sh;
+  load_share<5>(d.u_in, t, sh);
+  double g[5][6];
+  load_ghosts<5>(d.u_in, dir, a, b, g);
+  for (int i = t; i < 5 * P; i += Lds8::kThreads) acc[i] = 0.0;
+  store_share<5>(tin, t, sh);
+  __syncthreads();
+
+  double smax = 0.0;
+  double wm[N + 1], wp[N + 1];
+  {
+    Recon<5> rc;
+    double Fprev[5];
+    double q[5], Wm[5], Wp[5];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      double Ui[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k)
+        Ui[k] = (i >= kGhost && i < kGhost + N) ? tin[k * P + lbase + (i - kGhost) * lstride]
+                                                : g[k][i < kGhost ? i : i - N];
+      to_prim(Ui, q);
+      switch (i) {
+        case 0: rc.step<0>(q, Wm, Wp); break;
+        case 1: rc.step<1>(q, Wm, Wp); break;
+        case 2: rc.step<2>(q, Wm, Wp); break;
+        case 3: rc.step<3>(q, Wm, Wp); break;
+        case 4: rc.step<4>(q, Wm, Wp); break;
+        case 5: rc.step<5>(q, Wm, Wp); break;
+        default: rc.step<6>(q, Wm, Wp); break;
+      }
+      if (i >= 5) {
+        double Fh[5];
+        const int face = i - 5;  // face (i-3)+1/2, 0..N
+        smax = fmax(smax, core_flux(Wm, Wp, ex, ey, ez, Fh, wm[face], wp[face]));
+        if (i >= 6) {
+          const int cell = lbase + (i - 6) * lstride;   // interior cell of position i-3
+#pragma unroll
+          for (int k = 0; k < 5; ++k) {
+            const double df = Fh[k] - Fprev[k];
+            if (dir == 2)
+              held[k * P + cell] = tin[k * P + cell] - lambda * df;
+            else
+              atomicAdd(&acc[k * P + cell], df);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Fprev[k] = Fh[k];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+
+  // ---- finish the hydro core ---------------------------------------------
+  Share<1> ps;
+  double pg[1][6];
+  if (NP > 0) {
+    load_share<1>(d.u_in + 5 * FS, t, ps);
+    load_ghosts<1>(d.u_in + 5 * FS, dir, a, b, pg);
+  }
+  __syncthreads();   // hydro sums complete; tin free
+  if (dir == 2) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        const int cell = k * P + lbase + c * lstride;
+        d.u_out[k * FS + gline(2, a, b, c + kGhost)] = held[cell] - lambda * acc[cell];
+        acc[cell] = 0.0;
+      }
+    }
+  }
+
+  // ---- passive fields, one at a time --------------------------------------
+#pragma unroll 1
+  for (int p = 0; p < NP; ++p) {
+    store_share<1>(tin, t, ps);
+    double G[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) G[j] = pg[0][j];
+    __syncthreads();   // tin holds field 5+p; accumulator clear
+    if (p + 1 < NP) {
+      load_share<1>(d.u_in + (6 + p) * FS, t, ps);
+      load_ghosts<1>(d.u_in + (6 + p) * FS, dir, a, b, pg);
+    }
+    double L[N];
+    {
+      Recon<1> rc;
+      double Fprev = 0.0;
+      double q[1], Wm[1], Wp[1];
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        q[0] = (i >= kGhost && i < kGhost + N) ? tin[lbase + (i - kGhost) * lstride]
+                                               : G[i < kGhost ? i : i - N];
+        switch (i) {
+          case 0: rc.step<0>(q, Wm, Wp); break;
+          case 1: rc.step<1>(q, Wm, Wp); break;
+          case 2: rc.step<2>(q, Wm, Wp); break;
+          case 3: rc.step<3>(q, Wm, Wp); break;
+          case 4: rc.step<4>(q, Wm, Wp); break;
+          case 5: rc.step<5>(q, Wm, Wp); break;
+          default: rc.step<6>(q, Wm, Wp); break;
+        }
+        if (i >= 5) {
+          const int face = i - 5;
+          const double Fh = wm[face] * Wm[0] + wp[face] * Wp[0];
+          if (i >= 6) {
+            const int cell = lbase + (i - 6) * lstride;
+            const double df = Fh - Fprev;
+            if (dir == 2)
+              L[i - 6] = tin[cell] - lambda * df;
+            else
+              atomicAdd(&acc[cell], df);
+          }
+          Fprev = Fh;
+        }
+      }
+    }
+    __syncthreads();   // passive sums complete; tin free
+    if (dir == 2) {
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        const int cell = lbase + c * lstride;
+        d.u_out[(5 + p) * FS + gline(2, a, b, c + kGhost)] = L[c] - lambda * acc[cell];
+        acc[cell] = 0.0;
+      }
+    }
+  }
+
+  if (amax_out) {
+    smax = wave_max(smax);
+    if (l == 0) red[dir] = smax;
+    __syncthreads();
+    if (t == 0) amax_out[d.index] = fmax(fmax(red[0], red[1]), red[2]);
+  }
+}
+
+template <int F>
+__global__ void __launch_bounds__(Lds8::kThreads, 2)
+    hydro_lds8_kernel(const DevDesc* __restrict__ table, double dt, double dx,
+                      double* __restrict__ amax_out) {
+  const DevDesc d = table[blockIdx.x];
+  lds8_step<F>(d, dt, dx, amax_out);
+}
+
+template <int F>
+__global__ void __launch_bounds__(Lds8::kThreads, 2)
+    hydro_lds8_arg_kernel(ArgDescs descs, double dt, double dx,
+                          double* __restrict__ amax_out) {
+  const DevDesc d = descs.d[blockIdx.x];
+  lds8_step<F>(d, dt, dx, amax_out);
+}
+
+}  // namespace hydro

@@ -1,0 +1,110 @@
+"""Summarise rocprofv3 CSV output of bench.py runs into a short markdown
+profile and the per-launch HBM traffic record the benchmark reports.
+
+Inputs are the directories written by
+  rocprofv3 --kernel-trace --stats --output-format csv -d KT -o run -- python3 bench.py ...
+  rocprofv3 --pmc FETCH_SIZE --output-format csv -d FETCH -o run -- python3 bench.py ...
+  rocprofv3 --pmc WRITE_SIZE --output-format csv -d WRITE -o run -- python3 bench.py ...
+FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what the same
+counters read for the plain device copy that bench.py runs on the input
+buffer (known size), then reported per launch of the hydro kernel.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import json
+import os
+import statistics
+
+
+def _rows(d, name):
+    with open(os.path.join(d, name)) as f:
+        return list(csv.DictReader(f))
+
+
+def kernel_stats(kt_dir, match):
+    for r in _rows(kt_dir, "run_kernel_stats.csv"):
+        if match in r["Name"]:
+            return {"name": r["Name"], "calls": int(r["Calls"]),
+                    "avg_ns": float(r["AverageNs"]), "min_ns": float(r["MinNs"]),
+                    "max_ns": float(r["MaxNs"])}
+    raise SystemExit(f"kernel {match!r} not in kernel stats")
+
+
+def counter(d, match, name):
+    vals = [float(r["Counter_Value"]) for r in _rows(d, "run_counter_collection.csv")
+            if match in r["Kernel_Name"] and r["Counter_Name"] == name]
+    if not vals:
+        raise SystemExit(f"no {name} for {match!r} in {d}")
+    return vals
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--kt", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--kernel", required=True, help="substring of the hydro kernel name")
+    ap.add_argument("--copy-bytes", type=float, required=True,
+                    help="bytes the plain copy reads (= bytes it writes)")
+    ap.add_argument("--launch-bytes", type=float, required=True,
+                    help="algorithmic bytes of one hydro launch")
+    ap.add_argument("--version", required=True, help="hydro_version() of the profiled library")
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--command", required=True, help="the profiled command line")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--traffic-json", default=None)
+    a = ap.parse_args()
+
+    ks = kernel_stats(a.kt, a.kernel)
+    f_h = statistics.median(counter(a.fetch, a.kernel, "FETCH_SIZE"))
+    w_h = statistics.median(counter(a.write, a.kernel, "WRITE_SIZE"))
+    f_c = max(counter(a.fetch, "copyBuffer", "FETCH_SIZE"))
+    w_c = max(counter(a.write, "copyBuffer", "WRITE_SIZE"))
+    f_scale = a.copy_bytes / (f_c * 1024.0)
+    w_scale = a.copy_bytes / (w_c * 1024.0)
+    rd = f_h * 1024.0 * f_scale
+    wr = w_h * 1024.0 * w_scale
+    traffic = rd + wr
+    avg_s = ks["avg_ns"] * 1e-9
+    lines = [
+        f"# {ks['name']}",
+        "",
+        f"- workload: {a.workload}",
+        f"- library: `{a.version}`",
+        f"- command: `{a.command}`",
+        f"- counters: the same command with `--pmc FETCH_SIZE` and `--pmc WRITE_SIZE`"
+        " (one counter per run)",
+        "",
+        "| quantity | value |",
+        "|---|---|",
+        f"| launches traced | {ks['calls']} |",
+        f"| average duration | {ks['avg_ns'] / 1e3:.1f} us (min {ks['min_ns'] / 1e3:.1f}, max {ks['max_ns'] / 1e3:.1f}) |",
+        f"| FETCH_SIZE per launch (raw) | {f_h:.0f} KiB |",
+        f"| WRITE_SIZE per launch (raw) | {w_h:.0f} KiB |",
+        f"| copy calibration (bytes per counted byte) | read x{f_scale:.4f}, write x{w_scale:.4f} |",
+        f"| HBM read per launch | {rd / 1e6:.1f} MB |",
+        f"| HBM write per launch | {wr / 1e6:.1f} MB |",
+        f"| HBM traffic per launch | {traffic / 1e6:.1f} MB |",
+        f"| algorithmic bytes per launch | {a.launch_bytes / 1e6:.1f} MB |",
+        f"| traffic / algorithmic | {traffic / a.launch_bytes:.3f} |",
+        f"| algorithmic GB/s at average duration | {a.launch_bytes / avg_s / 1e9:.0f} |",
+        f"| traffic GB/s at average duration | {traffic / avg_s / 1e9:.0f} |",
+        "",
+    ]
+    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+    if a.traffic_json:
+        with open(a.traffic_json, "w") as f:
+            json.dump({"kernel_version": a.version, "kernel": ks["name"],
+                       "workload": a.workload, "traffic_bytes_per_launch": traffic,
+                       "read_bytes": rd, "write_bytes": wr,
+                       "avg_duration_us": ks["avg_ns"] / 1e3}, f, indent=1)
+            f.write("\n")
+
+
+if __name__ == "__main__":
+    main()
