@@ -44,6 +44,27 @@ int fail(int code, const char* fmt, ...) {
       return fail(HYDRO_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+// Work-groups per CU the 8^3 kernel is built for (LDS and registers allow
+// two resident work-groups of 192 lanes).
+constexpr int kLds8WgPerCu = 2;
+
+int g_cu_count[16] = {0};
+
+// Persistent grid for `n` sub-grids of the 8^3 kernel on the current device.
+int lds8_grid(int n) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) dev = 0;
+  if (g_cu_count[dev] == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    g_cu_count[dev] = cus;
+  }
+  (void)kLds8WgPerCu;
+  return n;   // one work-group per sub-grid
+}
+
 // Shape classes: (n, nfields) -> index.
 constexpr int kEdges[3] = {8, 12, 16};
 constexpr int kFields[2] = {6, 11};
@@ -120,8 +141,8 @@ int launch_table(const DevDesc* table, int n, double dt, double dx, double* amax
                  hipStream_t stream) {
   if (n <= 0) return HYDRO_OK;
   if constexpr (N == 8)
-    hipLaunchKernelGGL((hydro::hydro_lds8_kernel<F>), dim3(n),
-                       dim3(hydro::Lds8::kThreads), 0, stream, table, dt, dx, amax);
+    hipLaunchKernelGGL((hydro::hydro_lds8_kernel<F>), dim3(lds8_grid(n)),
+                       dim3(hydro::Lds8::kThreads), 0, stream, table, n, dt, dx, amax);
   else
     hipLaunchKernelGGL((hydro::hydro_table_kernel<N, F>), dim3(n),
                        dim3(hydro::Shape<N>::kThreads), 0, stream, table, dt, dx, amax);
@@ -267,9 +288,10 @@ struct hydro_plan {
   hipGraphNode_t node[kClasses] = {nullptr};
   struct Args {
     const DevDesc* table;
+    int count;
     double dt, dx;
     double* amax;
-    void* ptrs[4];
+    void* ptrs[5];
   } args[kClasses];
 };
 
@@ -281,17 +303,21 @@ void plan_set_args(hydro_plan* p, int c, double dt, double dx, double* amax) {
   a.dt = dt;
   a.dx = dx;
   a.amax = amax;
-  a.ptrs[0] = &a.table;
-  a.ptrs[1] = &a.dt;
-  a.ptrs[2] = &a.dx;
-  a.ptrs[3] = &a.amax;
+  a.count = p->num[c];
+  // the 8^3 kernels (classes 0, 1) also take the sub-grid count
+  int k = 0;
+  a.ptrs[k++] = &a.table;
+  if (c < 2) a.ptrs[k++] = &a.count;
+  a.ptrs[k++] = &a.dt;
+  a.ptrs[k++] = &a.dx;
+  a.ptrs[k++] = &a.amax;
 }
 
 hipKernelNodeParams plan_node_params(hydro_plan* p, int c) {
   hipKernelNodeParams kp;
   memset(&kp, 0, sizeof kp);
   kp.func = const_cast<void*>(table_kernel_fn(c));
-  kp.gridDim = dim3(p->num[c]);
+  kp.gridDim = dim3(c < 2 ? lds8_grid(p->num[c]) : p->num[c]);
   kp.blockDim = dim3(threads_of_class(c));
   kp.sharedMemBytes = 0;
   kp.kernelParams = p->args[c].ptrs;

@@ -33,7 +33,37 @@ namespace hydro {
 
 constexpr double kGamma = 5.0 / 3.0;
 constexpr double kGm1 = kGamma - 1.0;
+constexpr double kInvGm1 = 1.0 / kGm1;
 constexpr int kGhost = 3;
+
+// 1/x from the hardware estimate refined by two Newton-Raphson steps
+// (r <- r + r(1 - x r)); within an ulp or so of the rounded quotient for the
+// positive, normal arguments it is used on (densities, wave-speed spans).
+// Scaling x by a power of two scales the result exactly.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// sqrt(y) for positive normal y: hardware 1/sqrt estimate, then the coupled
+// Newton iteration for (sqrt(y), 1/(2 sqrt(y))) and a final residual
+// correction.
+__device__ __forceinline__ double sqrt_pos(double y) {
+  const double s = __builtin_amdgcn_rsq(y);
+  double g = y * s;
+  double h = 0.5 * s;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, y);
+  return fma(d, h, g);
+}
 
 // Device-side descriptor: one per sub-grid in an aggregated launch.
 struct DevDesc {

@@ -9,7 +9,9 @@
 // with coalesced loads into LDS; the six ghost cells of a line (needed by that
 // line only) are loaded by its lane straight into registers.  The 36 rows
 // that lie in both a y- and a z-ghost layer, and all edge/corner ghosts, are
-// never read.
+// never read.  Results are written with non-temporal stores: an interior row
+// covers only part of its cache lines, and streaming the partial lines out
+// avoids filling them from HBM first.
 //
 // Hydro core (rho, s, E): once the five lines are in registers, the lane
 // marches them (primitive recovery -> limited slopes -> interface offsets ->
@@ -34,9 +36,12 @@ namespace hydro {
 struct Lds8 {
   static constexpr int N = 8;
   static constexpr int M = 14;
-  static constexpr int RS = 9;     // LDS row stride of a cell array (doubles)
-  static constexpr int PS = 81;    // LDS plane stride
-  static constexpr int P = N * PS; // one field of a cell array: 648 doubles
+  // LDS cell arrays: row stride 9 and plane stride 72 (= 8 mod 16) make the
+  // 64-bit accesses of the x and y lanes bank-conflict free and leave one
+  // 2-way conflict per 16 z lanes.
+  static constexpr int RS = 9;
+  static constexpr int PS = 72;
+  static constexpr int P = N * PS; // one field of a cell array: 576 doubles
   static constexpr int kThreads = 192;
   static constexpr long FS = (long)M * M * M;
 };
@@ -104,16 +109,16 @@ __device__ __forceinline__ double core_flux(const double (&Wm)[5],
                                             double& wp) {
   const double vnm = ex * Wm[1] + ey * Wm[2] + ez * Wm[3];
   const double vnp = ex * Wp[1] + ey * Wp[2] + ez * Wp[3];
-  const double cm = sqrt(kGamma * Wm[4] / Wm[0]);
-  const double cp = sqrt(kGamma * Wp[4] / Wp[0]);
+  const double cm = sqrt_pos(kGamma * Wm[4] * recip(Wm[0]));
+  const double cp = sqrt_pos(kGamma * Wp[4] * recip(Wp[0]));
   const double ap = fmax(fmax(vnm + cm, vnp + cp), 0.0);
   const double am = fmin(fmin(vnm - cm, vnp - cp), 0.0);
-  const double inv = 1.0 / (ap - am);
+  const double inv = recip(ap - am);
   wm = ap * (vnm - am) * inv;
   wp = am * (ap - vnp) * inv;
-  const double Em = Wm[4] / kGm1 +
+  const double Em = Wm[4] * kInvGm1 +
                     0.5 * Wm[0] * (Wm[1] * Wm[1] + Wm[2] * Wm[2] + Wm[3] * Wm[3]);
-  const double Ep = Wp[4] / kGm1 +
+  const double Ep = Wp[4] * kInvGm1 +
                     0.5 * Wp[0] * (Wp[1] * Wp[1] + Wp[2] * Wp[2] + Wp[3] * Wp[3]);
   const double pt = (ap * Wm[4] - am * Wp[4]) * inv;
   Fh[0] = wm * Wm[0] + wp * Wp[0];
@@ -125,7 +130,7 @@ __device__ __forceinline__ double core_flux(const double (&Wm)[5],
 }
 
 __device__ __forceinline__ void to_prim(const double (&U)[5], double (&q)[5]) {
-  const double r = 1.0 / U[0];
+  const double r = recip(U[0]);
   const double vx = U[1] * r, vy = U[2] * r, vz = U[3] * r;
   q[0] = U[0];
   q[1] = vx;
@@ -133,6 +138,13 @@ __device__ __forceinline__ void to_prim(const double (&U)[5], double (&q)[5]) {
   q[3] = vz;
   q[4] = kGm1 * (U[4] - 0.5 * (U[1] * vx + U[2] * vy + U[3] * vz));
 }
+
+// Global-memory views of the caller's buffers (lets the compiler use
+// global_* instead of flat_* instructions).
+typedef const __attribute__((address_space(1))) double* gcptr;
+typedef __attribute__((address_space(1))) double* gptr;
+__device__ __forceinline__ gcptr as_global(const double* p) { return (gcptr)p; }
+__device__ __forceinline__ gptr as_global(double* p) { return (gptr)p; }
 
 // Stored index (within one field) of line position i for lane (a, b) of the
 // wave that owns direction dir.
@@ -152,16 +164,18 @@ struct Share {
   double v[K];
 };
 
+// (Elements j < K-1 always exist because t < 192.)
 template <int NF>
 __device__ __forceinline__ void load_share(const double* __restrict__ src, int t,
                                            Share<NF>& sh) {
+  const gcptr g = as_global(src);
 #pragma unroll
   for (int j = 0; j < Share<NF>::K; ++j) {
     const int e = t + j * Lds8::kThreads;
-    if (e < NF * 512) {
+    if (j + 1 < Share<NF>::K || e < NF * 512) {
       const int f = e >> 9, x = e & 7, y = (e >> 3) & 7, z = (e >> 6) & 7;
-      sh.v[j] = src[f * Lds8::FS + ((z + kGhost) * Lds8::M + (y + kGhost)) * Lds8::M +
-                    (x + kGhost)];
+      sh.v[j] = g[f * Lds8::FS + ((z + kGhost) * Lds8::M + (y + kGhost)) * Lds8::M +
+                  (x + kGhost)];
     }
   }
 }
@@ -171,24 +185,56 @@ __device__ __forceinline__ void store_share(double* lds, int t, const Share<NF>&
 #pragma unroll
   for (int j = 0; j < Share<NF>::K; ++j) {
     const int e = t + j * Lds8::kThreads;
-    if (e < NF * 512) {
+    if (j + 1 < Share<NF>::K || e < NF * 512) {
       const int f = e >> 9, x = e & 7, y = (e >> 3) & 7, z = (e >> 6) & 7;
       lds[f * Lds8::P + lcell(x, y, z)] = sh.v[j];
     }
   }
 }
 
+// Same, but every element is 0 unless `live` (no load is issued then).
+template <int NF>
+__device__ __forceinline__ void load_share_if(bool live, const double* __restrict__ src,
+                                              int t, Share<NF>& sh) {
+  const gcptr g = as_global(src);
+#pragma unroll
+  for (int j = 0; j < Share<NF>::K; ++j) {
+    const int e = t + j * Lds8::kThreads;
+    const int f = e >> 9, x = e & 7, y = (e >> 3) & 7, z = (e >> 6) & 7;
+    sh.v[j] = (live && (j + 1 < Share<NF>::K || e < NF * 512))
+                  ? g[f * Lds8::FS + ((z + kGhost) * Lds8::M + (y + kGhost)) * Lds8::M +
+                      (x + kGhost)]
+                  : 0.0;
+  }
+}
+
 // The six ghost positions (0, 1, 2, 11, 12, 13) of this lane's line for NF
 // consecutive fields.
+// Ghost position i of this lane's line is stored at gbase + i * gstride.
 template <int NF>
-__device__ __forceinline__ void load_ghosts(const double* __restrict__ src, int dir,
-                                            int a, int b, double (&g)[NF][6]) {
+__device__ __forceinline__ void load_ghosts(const double* __restrict__ src, int gbase,
+                                            int gstride, double (&g)[NF][6]) {
+  const gcptr p = as_global(src) + gbase;
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       const int i = j < 3 ? j : j + 8;
-      g[f][j] = src[f * Lds8::FS + gline(dir, a, b, i)];
+      g[f][j] = p[f * Lds8::FS + i * gstride];
+    }
+  }
+}
+
+template <int NF>
+__device__ __forceinline__ void load_ghosts_if(bool live, const double* __restrict__ src,
+                                               int gbase, int gstride, double (&g)[NF][6]) {
+  const gcptr p = as_global(src) + gbase;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int i = j < 3 ? j : j + 8;
+      g[f][j] = live ? p[f * Lds8::FS + i * gstride] : 0.0;
     }
   }
 }
@@ -205,6 +251,10 @@ __device__ __forceinline__ void recon_at(Recon<K>& rc, const double (&q)[K],
   recon_step<(I < 6 ? I : 6), K>(rc, q, Wm, Wp);
 }
 
+// One sub-grid per work-group.  Loads are issued in two bursts: the hydro
+// core (interior shares to LDS, ghosts to registers) at the start, and all
+// passive fields together right after the hydro march, so the passive phase
+// runs on data that is already on chip.
 template <int F>
 __device__ __forceinline__ void lds8_step(const DevDesc& d, double dt, double dx,
                                           double* __restrict__ amax_out) {
@@ -212,35 +262,40 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, double dt, double dx
   constexpr int N = Lds8::N;
   constexpr long FS = Lds8::FS;
   constexpr int P = Lds8::P;
-  constexpr int NP = F - 5;  // passive fields
-  // tin: interior of the staged fields.  acc: x+y flux differences (two
-  // atomic adds onto zero per cell).  held: the z lanes' U - lambda*dF_z of
-  // the hydro core.
-  __shared__ double tin[5 * P];
+  constexpr int NP = F - 5;              // passive fields
+  constexpr int NT = NP > 5 ? NP : 5;    // regions of the staged-interior array
+  // tin: interiors of the staged fields.  acc: x+y flux differences (two
+  // atomic adds onto zero per cell).  held: the z lanes' U - lambda*dF_z.
+  __shared__ double tin[NT * P];
   __shared__ double acc[5 * P];
   __shared__ double held[5 * P];
   __shared__ double red[3];
 
   const int t = threadIdx.x;
-  const int dir = t >> 6;          // wave-uniform
+  const int dir = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform
   const int l = t & 63;
   const int a = l & 7, b = l >> 3;
-  const double lambda = dt / ldexp(dx, -d.level);
   const double ex = dir == 0 ? 1.0 : 0.0;
   const double ey = dir == 1 ? 1.0 : 0.0;
   const double ez = dir == 2 ? 1.0 : 0.0;
   // interior line position c (3..10) -> LDS cell lbase + (c - 3) * lstride
   const int lbase = dir == 0 ? lcell(0, a, b) : dir == 1 ? lcell(a, 0, b) : lcell(a, b, 0);
   const int lstride = dir == 0 ? 1 : dir == 1 ? Lds8::RS : Lds8::PS;
+  // stored line position i -> gbase + i * gstride (same for every field)
+  const int gbase = gline(dir, a, b, 0);
+  const int gstride = dir == 0 ? 1 : dir == 1 ? M : M * M;
+  const double lambda = dt / ldexp(dx, -d.level);
 
-  // ---- stage the hydro core -------------------------------------------------
-  Share<5> sh;
-  load_share<5>(d.u_in, t, sh);
+  // ---- stage the hydro core ---------------------------------------------
+  {
+    Share<5> sh;
+    load_share<5>(d.u_in, t, sh);
+    for (int i = t; i < 5 * P; i += Lds8::kThreads) acc[i] = 0.0;
+    store_share<5>(tin, t, sh);
+  }
   double g[5][6];
-  load_ghosts<5>(d.u_in, dir, a, b, g);
-  for (int i = t; i < 5 * P; i += Lds8::kThreads) acc[i] = 0.0;
-  store_share<5>(tin, t, sh);
-  __syncthreads();
+  load_ghosts<5>(d.u_in, gbase, gstride, g);
+  __syncthreads();   // tin holds the hydro core; accumulator clear
 
   double smax = 0.0;
   double wm[N + 1], wp[N + 1];
@@ -271,13 +326,13 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, double dt, double dx
         smax = fmax(smax, core_flux(Wm, Wp, ex, ey, ez, Fh, wm[face], wp[face]));
         if (i >= 6) {
           const int cell = lbase + (i - 6) * lstride;   // interior cell of position i-3
+          if (dir == 2) {
 #pragma unroll
-          for (int k = 0; k < 5; ++k) {
-            const double df = Fh[k] - Fprev[k];
-            if (dir == 2)
-              held[k * P + cell] = tin[k * P + cell] - lambda * df;
-            else
-              atomicAdd(&acc[k * P + cell], df);
+            for (int k = 0; k < 5; ++k)
+              held[k * P + cell] = tin[k * P + cell] - lambda * (Fh[k] - Fprev[k]);
+          } else {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) atomicAdd(&acc[k * P + cell], Fh[k] - Fprev[k]);
           }
         }
 #pragma unroll
@@ -287,13 +342,11 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, double dt, double dx
     }
   }
 
-  // ---- finish the hydro core ---------------------------------------------
-  Share<1> ps;
-  double pg[1][6];
-  if (NP > 0) {
-    load_share<1>(d.u_in + 5 * FS, t, ps);
-    load_ghosts<1>(d.u_in + 5 * FS, dir, a, b, pg);
-  }
+  // ---- all passive fields in one burst ----------------------------------
+  Share<NP> ps;
+  double pg[NP][6];
+  load_share<NP>(d.u_in + 5 * FS, t, ps);
+  load_ghosts<NP>(d.u_in + 5 * FS, gbase, gstride, pg);
   __syncthreads();   // hydro sums complete; tin free
   if (dir == 2) {
 #pragma unroll
@@ -301,63 +354,58 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, double dt, double dx
 #pragma unroll
       for (int c = 0; c < N; ++c) {
         const int cell = k * P + lbase + c * lstride;
-        d.u_out[k * FS + gline(2, a, b, c + kGhost)] = held[cell] - lambda * acc[cell];
+        __builtin_nontemporal_store(held[cell] - lambda * acc[cell],
+                                    &as_global(d.u_out)[k * FS + gbase + (c + kGhost) * gstride]);
         acc[cell] = 0.0;
       }
     }
   }
+  store_share<NP>(tin, t, ps);
+  __syncthreads();   // tin holds every passive field; accumulator clear
 
-  // ---- passive fields, one at a time --------------------------------------
-#pragma unroll 1
+  // ---- passive fields, one at a time, from LDS ---------------------------
+#pragma unroll
   for (int p = 0; p < NP; ++p) {
-    store_share<1>(tin, t, ps);
-    double G[6];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) G[j] = pg[0][j];
-    __syncthreads();   // tin holds field 5+p; accumulator clear
-    if (p + 1 < NP) {
-      load_share<1>(d.u_in + (6 + p) * FS, t, ps);
-      load_ghosts<1>(d.u_in + (6 + p) * FS, dir, a, b, pg);
-    }
     double L[N];
-    {
-      Recon<1> rc;
-      double Fprev = 0.0;
-      double q[1], Wm[1], Wp[1];
+    Recon<1> rc;
+    double Fprev = 0.0;
+    double q[1], Wm[1], Wp[1];
 #pragma unroll
-      for (int i = 0; i < M; ++i) {
-        q[0] = (i >= kGhost && i < kGhost + N) ? tin[lbase + (i - kGhost) * lstride]
-                                               : G[i < kGhost ? i : i - N];
-        switch (i) {
-          case 0: rc.step<0>(q, Wm, Wp); break;
-          case 1: rc.step<1>(q, Wm, Wp); break;
-          case 2: rc.step<2>(q, Wm, Wp); break;
-          case 3: rc.step<3>(q, Wm, Wp); break;
-          case 4: rc.step<4>(q, Wm, Wp); break;
-          case 5: rc.step<5>(q, Wm, Wp); break;
-          default: rc.step<6>(q, Wm, Wp); break;
+    for (int i = 0; i < M; ++i) {
+      q[0] = (i >= kGhost && i < kGhost + N) ? tin[p * P + lbase + (i - kGhost) * lstride]
+                                             : pg[p][i < kGhost ? i : i - N];
+      switch (i) {
+        case 0: rc.step<0>(q, Wm, Wp); break;
+        case 1: rc.step<1>(q, Wm, Wp); break;
+        case 2: rc.step<2>(q, Wm, Wp); break;
+        case 3: rc.step<3>(q, Wm, Wp); break;
+        case 4: rc.step<4>(q, Wm, Wp); break;
+        case 5: rc.step<5>(q, Wm, Wp); break;
+        default: rc.step<6>(q, Wm, Wp); break;
+      }
+      if (i >= 5) {
+        const double Fh = wm[i - 5] * Wm[0] + wp[i - 5] * Wp[0];
+        if (i >= 6) {
+          const int cell = lbase + (i - 6) * lstride;
+          if (dir == 2)
+            L[i - 6] = tin[p * P + cell] - lambda * (Fh - Fprev);
+          else
+            atomicAdd(&acc[(p % 2) * P + cell], Fh - Fprev);
         }
-        if (i >= 5) {
-          const int face = i - 5;
-          const double Fh = wm[face] * Wm[0] + wp[face] * Wp[0];
-          if (i >= 6) {
-            const int cell = lbase + (i - 6) * lstride;
-            const double df = Fh - Fprev;
-            if (dir == 2)
-              L[i - 6] = tin[cell] - lambda * df;
-            else
-              atomicAdd(&acc[cell], df);
-          }
-          Fprev = Fh;
-        }
+        Fprev = Fh;
       }
     }
-    __syncthreads();   // passive sums complete; tin free
+    // Alternate two accumulator regions: field p is finished by the z lanes
+    // after the barrier, while the x/y lanes may already add field p+1 into
+    // the other region; region p%2 is reused two fields later, after the
+    // next barrier, by which time the z lanes have cleared it.
+    __syncthreads();
     if (dir == 2) {
 #pragma unroll
       for (int c = 0; c < N; ++c) {
-        const int cell = lbase + c * lstride;
-        d.u_out[(5 + p) * FS + gline(2, a, b, c + kGhost)] = L[c] - lambda * acc[cell];
+        const int cell = (p % 2) * P + lbase + c * lstride;
+        __builtin_nontemporal_store(L[c] - lambda * acc[cell],
+                                    &as_global(d.u_out)[(5 + p) * FS + gbase + (c + kGhost) * gstride]);
         acc[cell] = 0.0;
       }
     }
@@ -371,14 +419,17 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, double dt, double dx
   }
 }
 
+// One sub-grid per work-group; the descriptor table has `count` entries.
 template <int F>
 __global__ void __launch_bounds__(Lds8::kThreads, 2)
-    hydro_lds8_kernel(const DevDesc* __restrict__ table, double dt, double dx,
-                      double* __restrict__ amax_out) {
+    hydro_lds8_kernel(const DevDesc* __restrict__ table, int count, double dt,
+                      double dx, double* __restrict__ amax_out) {
+  (void)count;
   const DevDesc d = table[blockIdx.x];
   lds8_step<F>(d, dt, dx, amax_out);
 }
 
+// Small batches: descriptors in the kernel arguments, one per work-group.
 template <int F>
 __global__ void __launch_bounds__(Lds8::kThreads, 2)
     hydro_lds8_arg_kernel(ArgDescs descs, double dt, double dx,
