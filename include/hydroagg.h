@@ -110,6 +110,87 @@ int hydro_plan_launch_graph(hydro_plan_t *plan, double dt, double dx,
                             double *amax_dev, void *stream);
 int hydro_plan_destroy(hydro_plan_t *plan);
 
+/*
+ * Aggregator: explicit work aggregation of fine-grained sub-grid tasks (the
+ * paper's strategy 3, Section V-D).  Tasks submitted while the aggregator's
+ * streams are busy are held and launched together as one batch (one kernel
+ * per shape class) when the batch reaches max_width (the paper's "max
+ * aggregated kernels"; 1 disables aggregation), when a stream is idle (if
+ * flush_when_idle), when the oldest held task is timeout_us old (< 0: never),
+ * on hydro_flush, or when a task with a different (dt, dx) arrives.
+ * Admission is bounded: held plus in-flight tasks may not own more than
+ * hbm_budget_bytes of output (0 = unbounded); hydro_submit then returns
+ * HYDRO_EAGAIN and the caller retries after hydro_progress / completions.
+ * n_streams (1..8) streams and all batch buffers are created by
+ * hydro_agg_create; submit/flush/progress/poll never allocate.  Calls on one
+ * aggregator are serialised by an internal mutex.  If a launch that
+ * hydro_submit triggers fails (HYDRO_EHIP), the task stays held with its
+ * ticket set and a later flush retries it.  A ticket identifies one
+ * task; its result (amax of the sub-grid) is retrieved once, by hydro_poll
+ * (non-blocking) or hydro_wait (blocking).  hydro_agg_destroy launches held
+ * tasks and waits for all work.
+ */
+typedef struct hydro_agg hydro_agg_t;
+
+typedef struct {
+  uint64_t submitted, batches, launched;
+  uint64_t flush_width, flush_idle, flush_timeout, flush_manual;
+  uint64_t refused;            /* HYDRO_EAGAIN answers                        */
+  uint64_t width_hist[11];     /* batches of width 1, 2-3, 4-7, ..., >= 1024  */
+  uint64_t held, held_bytes;   /* tasks held now; output bytes held+in flight */
+} hydro_agg_stats_t;
+
+int hydro_agg_create(hydro_agg_t **out, int32_t max_width, double timeout_us,
+                     int32_t n_streams, uint64_t hbm_budget_bytes,
+                     int32_t flush_when_idle);
+int hydro_submit(hydro_agg_t *agg, const hydro_subgrid_t *sg, double dt,
+                 double dx, uint64_t *ticket);
+int hydro_flush(hydro_agg_t *agg);     /* launch whatever is held now        */
+int hydro_progress(hydro_agg_t *agg);  /* collect completions; apply the
+                                          timeout / idle-stream rules        */
+int hydro_poll(hydro_agg_t *agg, uint64_t ticket, int32_t *done, double *amax);
+int hydro_wait(hydro_agg_t *agg, uint64_t ticket, double *amax);
+int hydro_agg_stats(hydro_agg_t *agg, hydro_agg_stats_t *out);
+int hydro_agg_destroy(hydro_agg_t *agg);
+
+/*
+ * Serving loop (continuous batching on device-resident state).  `pool` holds
+ * resident sub-grids (u_in used; u_out ignored).  Task i steps sub-grid
+ * task_subgrid[i] and arrives at arrival_us[i] (microseconds after the loop
+ * starts, non-decreasing; the caller draws them, e.g. Poisson).  An arrived
+ * task is admitted as soon as an output slab of its edge class is free
+ * (slabs[e] slabs of (n+6)^3 x nfields doubles at slab_base[e] for
+ * n = 8, 12, 16 -- the HBM budget of the loop), is submitted to an
+ * aggregator configured by cfg, and releases its slab when its batch has
+ * completed (unless keep_slabs).  Per task the loop reports latency_us =
+ * completion observed - arrival, and optionally amax and the slab used.
+ * Runs on the calling thread until every task has completed.
+ */
+typedef struct {
+  int32_t max_width;
+  double timeout_us;
+  int32_t n_streams;
+  int32_t flush_when_idle;
+  int32_t nfields;
+  double dt, dx;
+  double *slab_base[3];
+  int32_t slabs[3];
+  int32_t keep_slabs;
+} hydro_serve_config_t;
+
+typedef struct {
+  hydro_agg_stats_t agg;
+  double makespan_us;      /* last completion, from loop start             */
+  double first_admit_us;
+  uint64_t max_live;       /* most tasks admitted and not yet completed    */
+  uint64_t slab_waits;     /* loop passes where an arrived task had no slab */
+} hydro_serve_stats_t;
+
+int hydro_serve_run(const hydro_serve_config_t *cfg, const hydro_subgrid_t *pool,
+                    int32_t pool_count, const int32_t *task_subgrid,
+                    const double *arrival_us, int32_t ntasks, double *latency_us,
+                    double *amax_out, double **out_slab, hydro_serve_stats_t *stats);
+
 /* Thread-local text of the last error on the calling thread ("" if none). */
 const char *hydro_last_error(void);
 

@@ -1,0 +1,486 @@
+// agg_api.hip -- the submit/flush aggregator on HIP streams, and a
+// continuous-batching serving loop built on it.
+//
+// The aggregator (paper Section V-D, strategy 3) holds sub-grid tasks while
+// its streams are busy and launches them as one batch (one kernel per shape
+// class) by the rules of agg_policy.hpp.  Every resource a batch needs -- a
+// pinned descriptor table, a device descriptor table, a device amax array and
+// its pinned copy, an event -- comes from slots allocated at create time, as
+// are the streams: nothing is allocated or created on the submit path
+// (Section V-C).
+#include <hip/hip_runtime.h>
+
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <deque>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "agg_policy.hpp"
+#include "internal.hpp"
+
+using hydro::DevDesc;
+using hydro::Task;
+using hydro::api::fail;
+
+namespace {
+
+#define HIP_OK(expr)                                                         \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return fail(HYDRO_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+struct SteadyClock {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  double now_us() const {
+    return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0)
+        .count();
+  }
+};
+
+// Executor on HIP streams.
+class HipExec {
+ public:
+  int init(int nstreams, int width, int slots_per_stream) {
+    ns_ = nstreams;
+    cap_ = width;
+    for (int s = 0; s < ns_; ++s) {
+      HIP_OK(hipStreamCreateWithFlags(&streams_[s], hipStreamNonBlocking));
+      created_ = s + 1;
+    }
+    slots_.resize((size_t)ns_ * slots_per_stream);
+    for (Slot& sl : slots_) {
+      HIP_OK(hipHostMalloc((void**)&sl.htab, sizeof(DevDesc) * cap_, hipHostMallocDefault));
+      HIP_OK(hipMalloc((void**)&sl.dtab, sizeof(DevDesc) * cap_));
+      HIP_OK(hipMalloc((void**)&sl.damax, sizeof(double) * cap_));
+      HIP_OK(hipHostMalloc((void**)&sl.hamax, sizeof(double) * cap_, hipHostMallocDefault));
+      HIP_OK(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+    }
+    return HYDRO_OK;
+  }
+
+  void teardown() {
+    for (int s = 0; s < created_; ++s) (void)hipStreamSynchronize(streams_[s]);
+    for (Slot& sl : slots_) {
+      if (sl.ev) (void)hipEventDestroy(sl.ev);
+      if (sl.htab) (void)hipHostFree(sl.htab);
+      if (sl.hamax) (void)hipHostFree(sl.hamax);
+      if (sl.dtab) (void)hipFree(sl.dtab);
+      if (sl.damax) (void)hipFree(sl.damax);
+    }
+    slots_.clear();
+    for (int s = 0; s < created_; ++s) (void)hipStreamDestroy(streams_[s]);
+    created_ = 0;
+  }
+
+  int streams() const { return ns_; }
+  hipStream_t stream(int s) const { return streams_[s]; }
+
+  bool idle(int s) {
+    for (auto& kv : live_) {
+      Slot& sl = slots_[kv.second];
+      if (sl.stream == s && !sl.finished) {
+        if (hipEventQuery(sl.ev) != hipSuccess) return false;
+        sl.finished = true;
+      }
+    }
+    return true;
+  }
+
+  int launch(int s, const Task* t, int n, double dt, double dx, uint64_t batch) {
+    if (n > cap_) return fail(HYDRO_ENOMEM, "batch of %d exceeds the width %d", n, cap_);
+    int k = free_slot();
+    if (k < 0) {
+      int rc = retire_oldest();
+      if (rc) return rc;
+      k = free_slot();
+      if (k < 0) return fail(HYDRO_ENOMEM, "no batch slot");
+    }
+    Slot& sl = slots_[k];
+    int num[hydro::api::kNumClasses] = {0}, off[hydro::api::kNumClasses], fill[hydro::api::kNumClasses];
+    for (int i = 0; i < n; ++i) num[hydro::api::class_of_task(t[i].n, t[i].nfields)]++;
+    int pos = 0;
+    for (int c = 0; c < hydro::api::kNumClasses; ++c) {
+      off[c] = fill[c] = pos;
+      pos += num[c];
+    }
+    for (int i = 0; i < n; ++i) {
+      DevDesc& d = sl.htab[fill[hydro::api::class_of_task(t[i].n, t[i].nfields)]++];
+      d.u_in = t[i].u_in;
+      d.u_out = t[i].u_out;
+      d.level = t[i].level;
+      d.index = i;
+    }
+    hipStream_t st = streams_[s];
+    HIP_OK(hipMemcpyAsync(sl.dtab, sl.htab, sizeof(DevDesc) * n, hipMemcpyHostToDevice, st));
+    for (int c = 0; c < hydro::api::kNumClasses; ++c) {
+      if (!num[c]) continue;
+      int rc = hydro::api::launch_class(c, sl.dtab + off[c], num[c], dt, dx, sl.damax, st);
+      if (rc) return rc;
+    }
+    HIP_OK(hipMemcpyAsync(sl.hamax, sl.damax, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipEventRecord(sl.ev, st));
+    sl.busy = true;
+    sl.finished = false;
+    sl.stream = s;
+    sl.n = n;
+    sl.batch = batch;
+    live_[batch] = k;
+    order_.push_back(batch);
+    return HYDRO_OK;
+  }
+
+  bool done(uint64_t batch) {
+    auto r = retired_.find(batch);
+    if (r != retired_.end()) return true;
+    Slot& sl = slots_[live_.at(batch)];
+    if (sl.finished) return true;
+    if (hipEventQuery(sl.ev) == hipSuccess) sl.finished = true;
+    return sl.finished;
+  }
+
+  int wait(uint64_t batch) {
+    if (retired_.count(batch)) return HYDRO_OK;
+    Slot& sl = slots_[live_.at(batch)];
+    HIP_OK(hipEventSynchronize(sl.ev));
+    sl.finished = true;
+    return HYDRO_OK;
+  }
+
+  void results(uint64_t batch, double* amax) {
+    auto r = retired_.find(batch);
+    if (r != retired_.end()) {
+      std::copy(r->second.begin(), r->second.end(), amax);
+      return;
+    }
+    Slot& sl = slots_[live_.at(batch)];
+    std::copy(sl.hamax, sl.hamax + sl.n, amax);
+  }
+
+  void release(uint64_t batch) {
+    auto r = retired_.find(batch);
+    if (r != retired_.end()) {
+      retired_.erase(r);
+      return;
+    }
+    auto it = live_.find(batch);
+    if (it == live_.end()) return;
+    slots_[it->second].busy = false;
+    live_.erase(it);
+    order_.erase(std::find(order_.begin(), order_.end(), batch));
+  }
+
+ private:
+  struct Slot {
+    DevDesc* htab = nullptr;
+    DevDesc* dtab = nullptr;
+    double* damax = nullptr;
+    double* hamax = nullptr;
+    hipEvent_t ev = nullptr;
+    bool busy = false, finished = false;
+    int stream = 0, n = 0;
+    uint64_t batch = 0;
+  };
+
+  int free_slot() const {
+    for (size_t k = 0; k < slots_.size(); ++k)
+      if (!slots_[k].busy) return (int)k;
+    return -1;
+  }
+
+  // All slots in use: wait for the oldest batch, keep its results on the host.
+  int retire_oldest() {
+    const uint64_t b = order_.front();
+    Slot& sl = slots_[live_.at(b)];
+    HIP_OK(hipEventSynchronize(sl.ev));
+    retired_[b] = std::vector<double>(sl.hamax, sl.hamax + sl.n);
+    sl.busy = false;
+    live_.erase(b);
+    order_.pop_front();
+    return HYDRO_OK;
+  }
+
+  int ns_ = 0, created_ = 0, cap_ = 0;
+  hipStream_t streams_[8] = {};
+  std::vector<Slot> slots_;
+  std::unordered_map<uint64_t, int> live_;
+  std::deque<uint64_t> order_;
+  std::unordered_map<uint64_t, std::vector<double>> retired_;
+};
+
+using Policy = hydro::AggPolicy<HipExec, SteadyClock>;
+
+uint64_t task_bytes(const hydro_subgrid_t& s) {
+  const uint64_t M = (uint64_t)s.n + 2 * HYDRO_GHOST;
+  return (uint64_t)s.nfields * M * M * M * sizeof(double);
+}
+
+}  // namespace
+
+struct hydro_agg {
+  std::mutex mu;
+  HipExec ex;
+  SteadyClock clk;
+  Policy* pol = nullptr;
+  int width = 1;
+};
+
+extern "C" {
+
+int hydro_agg_create(hydro_agg_t** out, int32_t max_width, double timeout_us,
+                     int32_t n_streams, uint64_t hbm_budget_bytes, int32_t flush_when_idle) {
+  hydro::api::clear_error();
+  if (!out) return fail(HYDRO_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (max_width < 1 || max_width > 65536) return fail(HYDRO_EINVAL, "max_width %d", max_width);
+  if (n_streams < 1 || n_streams > 8) return fail(HYDRO_EINVAL, "n_streams %d", n_streams);
+  if (timeout_us != timeout_us) return fail(HYDRO_EINVAL, "timeout is NaN");
+  hydro_agg* a = new hydro_agg();
+  a->width = max_width;
+  int rc = a->ex.init(n_streams, max_width, 8);
+  if (rc) {
+    a->ex.teardown();
+    delete a;
+    return rc;
+  }
+  a->pol = new Policy(a->ex, a->clk, max_width, timeout_us, hbm_budget_bytes, flush_when_idle != 0);
+  *out = a;
+  return HYDRO_OK;
+}
+
+int hydro_submit(hydro_agg_t* a, const hydro_subgrid_t* sg, double dt, double dx,
+                 uint64_t* ticket) {
+  hydro::api::clear_error();
+  if (!a || !ticket) return fail(HYDRO_EINVAL, "NULL aggregator or ticket");
+  int rc = hydro::api::validate_batch(sg, 1, dt, dx);
+  if (rc) return rc;
+  Task t;
+  t.u_in = sg->u_in;
+  t.u_out = sg->u_out;
+  t.n = sg->n;
+  t.nfields = sg->nfields;
+  t.level = sg->level;
+  t.bytes = task_bytes(*sg);
+  std::lock_guard<std::mutex> lk(a->mu);
+  rc = a->pol->submit(t, dt, dx, ticket);
+  if (rc == HYDRO_EAGAIN) return fail(HYDRO_EAGAIN, "admission refused: byte budget in use");
+  return rc;
+}
+
+int hydro_flush(hydro_agg_t* a) {
+  hydro::api::clear_error();
+  if (!a) return fail(HYDRO_EINVAL, "NULL aggregator");
+  std::lock_guard<std::mutex> lk(a->mu);
+  return a->pol->flush();
+}
+
+int hydro_progress(hydro_agg_t* a) {
+  hydro::api::clear_error();
+  if (!a) return fail(HYDRO_EINVAL, "NULL aggregator");
+  std::lock_guard<std::mutex> lk(a->mu);
+  return a->pol->progress();
+}
+
+int hydro_poll(hydro_agg_t* a, uint64_t ticket, int32_t* done, double* amax) {
+  hydro::api::clear_error();
+  if (!a || !done) return fail(HYDRO_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(a->mu);
+  int d = 0;
+  int rc = a->pol->poll(ticket, &d, amax);
+  if (rc == -1) return fail(HYDRO_EINVAL, "unknown or already retrieved ticket %llu",
+                            (unsigned long long)ticket);
+  *done = d;
+  return rc;
+}
+
+int hydro_wait(hydro_agg_t* a, uint64_t ticket, double* amax) {
+  hydro::api::clear_error();
+  if (!a) return fail(HYDRO_EINVAL, "NULL aggregator");
+  std::lock_guard<std::mutex> lk(a->mu);
+  int rc = a->pol->wait(ticket, amax);
+  if (rc == -1) return fail(HYDRO_EINVAL, "unknown or already retrieved ticket %llu",
+                            (unsigned long long)ticket);
+  return rc;
+}
+
+int hydro_agg_stats(hydro_agg_t* a, hydro_agg_stats_t* out) {
+  hydro::api::clear_error();
+  if (!a || !out) return fail(HYDRO_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(a->mu);
+  const hydro::AggStats& s = a->pol->stats();
+  memset(out, 0, sizeof *out);
+  out->submitted = s.submitted;
+  out->batches = s.launched_batches;
+  out->launched = s.launched_tasks;
+  out->flush_width = s.flush_width;
+  out->flush_idle = s.flush_idle;
+  out->flush_timeout = s.flush_timeout;
+  out->flush_manual = s.flush_manual + s.flush_param;
+  out->refused = s.refused;
+  for (int i = 0; i < 11; ++i) out->width_hist[i] = s.width_hist[i];
+  out->held = a->pol->held();
+  out->held_bytes = a->pol->held_bytes();
+  return HYDRO_OK;
+}
+
+int hydro_agg_destroy(hydro_agg_t* a) {
+  hydro::api::clear_error();
+  if (!a) return HYDRO_OK;
+  int rc;
+  {
+    std::lock_guard<std::mutex> lk(a->mu);
+    rc = a->pol->drain();
+  }
+  delete a->pol;
+  a->ex.teardown();
+  delete a;
+  return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving loop
+// ---------------------------------------------------------------------------
+namespace {
+
+// Free output slabs of one edge class, carved from caller-provided device
+// memory (the HBM budget of the loop).
+struct SlabPool {
+  std::vector<double*> free_list;
+};
+
+}  // namespace
+
+extern "C" int hydro_serve_run(const hydro_serve_config_t* cfg, const hydro_subgrid_t* pool,
+                               int32_t pool_count, const int32_t* task_subgrid,
+                               const double* arrival_us, int32_t ntasks,
+                               double* latency_us, double* amax_out, double** out_slab,
+                               hydro_serve_stats_t* stats) {
+  hydro::api::clear_error();
+  if (!cfg || !pool || pool_count <= 0 || !task_subgrid || !arrival_us || ntasks < 0 ||
+      !latency_us || !stats)
+    return fail(HYDRO_EINVAL, "NULL or empty argument");
+  if (cfg->max_width < 1 || cfg->n_streams < 1) return fail(HYDRO_EINVAL, "bad aggregator config");
+  int rc = HYDRO_OK;
+  for (int i = 1; i < ntasks; ++i)
+    if (!(arrival_us[i] >= arrival_us[i - 1]))
+      return fail(HYDRO_EINVAL, "arrival times must be non-decreasing");
+  // slab pools per edge class
+  SlabPool pools[3];
+  for (int e = 0; e < 3; ++e) {
+    const int n = 8 + 4 * e;
+    if (cfg->slabs[e] < 0) return fail(HYDRO_EINVAL, "negative slab count");
+    if (cfg->slabs[e] > 0 && !cfg->slab_base[e]) return fail(HYDRO_EINVAL, "NULL slab arena");
+    const uint64_t M = (uint64_t)n + 2 * HYDRO_GHOST;
+    const uint64_t words = (uint64_t)cfg->nfields * M * M * M;
+    for (int k = cfg->slabs[e] - 1; k >= 0; --k)
+      pools[e].free_list.push_back(cfg->slab_base[e] + (uint64_t)k * words);
+  }
+  // every resident sub-grid must be a valid task with an output slab of its class
+  for (int s = 0; s < pool_count; ++s) {
+    if (hydro::api::class_of_task(pool[s].n, pool[s].nfields) < 0 || pool[s].nfields != cfg->nfields)
+      return fail(HYDRO_EINVAL, "sub-grid %d: n=%d nfields=%d", s, pool[s].n, pool[s].nfields);
+    const int e = (pool[s].n - 8) / 4;
+    if (cfg->slabs[e] == 0) return fail(HYDRO_EINVAL, "sub-grid %d: no slabs for n=%d", s, pool[s].n);
+    hydro_subgrid_t probe = pool[s];
+    probe.u_out = cfg->slab_base[e];
+    rc = hydro::api::validate_batch(&probe, 1, cfg->dt, cfg->dx);
+    if (rc) return rc;
+  }
+  for (int i = 0; i < ntasks; ++i)
+    if (task_subgrid[i] < 0 || task_subgrid[i] >= pool_count)
+      return fail(HYDRO_EINVAL, "task %d: sub-grid %d", i, task_subgrid[i]);
+
+  hydro_agg_t* agg = nullptr;
+  rc = hydro_agg_create(&agg, cfg->max_width, cfg->timeout_us, cfg->n_streams, 0,
+                        cfg->flush_when_idle);
+  if (rc) return rc;
+  agg->pol->record_completions(true);
+
+  struct Live {
+    int task;
+    int cls;
+    double* slab;
+  };
+  std::deque<int> waiting[3];  // arrived, waiting for an output slab
+  std::unordered_map<uint64_t, Live> live;
+  std::vector<std::pair<uint64_t, double>> done;
+  SteadyClock clk;
+  int next = 0, finished = 0;
+  uint64_t max_live = 0, slab_waits = 0;
+  double t_first = -1.0, t_last = 0.0;
+  const double t0 = clk.now_us();
+  while (finished < ntasks && rc == HYDRO_OK) {
+    const double now = clk.now_us() - t0;
+    // 1. arrivals
+    while (next < ntasks && arrival_us[next] <= now) {
+      waiting[(pool[task_subgrid[next]].n - 8) / 4].push_back(next);
+      ++next;
+    }
+    // 2. admission: a task enters as soon as an output slab of its class is
+    //    free, and joins whatever batch the aggregator is forming
+    for (int e = 0; e < 3 && rc == HYDRO_OK; ++e) {
+      while (!waiting[e].empty() && !pools[e].free_list.empty()) {
+        const int i = waiting[e].front();
+        waiting[e].pop_front();
+        double* slab = pools[e].free_list.back();
+        pools[e].free_list.pop_back();
+        Task t;
+        const hydro_subgrid_t& src = pool[task_subgrid[i]];
+        t.u_in = src.u_in;
+        t.u_out = slab;
+        t.n = src.n;
+        t.nfields = src.nfields;
+        t.level = src.level;
+        t.bytes = task_bytes(src);
+        uint64_t ticket = 0;
+        rc = agg->pol->submit(t, cfg->dt, cfg->dx, &ticket);
+        if (rc) break;
+        live[ticket] = Live{i, e, slab};
+        if (t_first < 0) t_first = now;
+      }
+      if (!waiting[e].empty()) slab_waits++;
+    }
+    if (rc) break;
+    max_live = std::max<uint64_t>(max_live, live.size());
+    // 3. flush rules (timeout, idle stream) and completions
+    rc = agg->pol->progress();
+    if (rc) break;
+    agg->pol->take_completed(done);
+    if (!done.empty()) {
+      const double t_done = clk.now_us() - t0;
+      for (auto& c : done) {
+        auto it = live.find(c.first);
+        const Live lv = it->second;
+        live.erase(it);
+        latency_us[lv.task] = t_done - arrival_us[lv.task];
+        if (amax_out) amax_out[lv.task] = c.second;
+        if (out_slab) out_slab[lv.task] = lv.slab;
+        if (!cfg->keep_slabs) pools[lv.cls].free_list.push_back(lv.slab);
+        ++finished;
+      }
+      t_last = t_done;
+    }
+  }
+  if (rc == HYDRO_OK) {
+    hydro_agg_stats_t as;
+    hydro_agg_stats(agg, &as);
+    memset(stats, 0, sizeof *stats);
+    stats->agg = as;
+    stats->makespan_us = t_last;
+    stats->first_admit_us = t_first;
+    stats->max_live = max_live;
+    stats->slab_waits = slab_waits;
+  }
+  {
+    const int rc2 = hydro_agg_destroy(agg);
+    if (!rc) rc = rc2;
+  }
+  return rc;
+}

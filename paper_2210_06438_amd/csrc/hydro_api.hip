@@ -25,7 +25,8 @@
 using hydro::ArgDescs;
 using hydro::DevDesc;
 
-namespace {
+namespace hydro {
+namespace api {
 
 thread_local char g_err[512] = "";
 
@@ -36,6 +37,16 @@ int fail(int code, const char* fmt, ...) {
   va_end(ap);
   return code;
 }
+
+void clear_error() { g_err[0] = '\0'; }
+
+}  // namespace api
+}  // namespace hydro
+
+using hydro::api::fail;
+using hydro::api::g_err;
+
+namespace {
 
 #define HIP_TRY(expr)                                                       \
   do {                                                                      \
@@ -274,6 +285,19 @@ int step_chunk(DeviceState* st, const hydro_subgrid_t* sg, int count, int base,
 }
 
 }  // namespace
+
+namespace hydro {
+namespace api {
+int class_of_task(int n, int nf) { return class_of(n, nf); }
+int validate_batch(const hydro_subgrid_t* sg, int32_t count, double dt, double dx) {
+  return validate(sg, count, dt, dx);
+}
+int launch_class(int cls, const DevDesc* table, int n, double dt, double dx, double* amax,
+                 hipStream_t s) {
+  return dispatch_table(cls, table, n, dt, dx, amax, s);
+}
+}  // namespace api
+}  // namespace hydro
 
 // ---- plans ---------------------------------------------------------------
 struct hydro_plan {

@@ -36,6 +36,32 @@ class hydro_subgrid_t(ctypes.Structure):
 
 assert ctypes.sizeof(hydro_subgrid_t) == 32
 
+
+class hydro_agg_stats_t(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "submitted", "batches", "launched", "flush_width", "flush_idle", "flush_timeout",
+        "flush_manual", "refused")] + [("width_hist", ctypes.c_uint64 * 11),
+                                       ("held", ctypes.c_uint64), ("held_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        d = {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "width_hist"}
+        d["width_hist"] = [int(x) for x in self.width_hist]
+        return d
+
+
+class hydro_serve_config_t(ctypes.Structure):
+    _fields_ = [("max_width", ctypes.c_int32), ("timeout_us", ctypes.c_double),
+                ("n_streams", ctypes.c_int32), ("flush_when_idle", ctypes.c_int32),
+                ("nfields", ctypes.c_int32), ("dt", ctypes.c_double), ("dx", ctypes.c_double),
+                ("slab_base", ctypes.c_void_p * 3), ("slabs", ctypes.c_int32 * 3),
+                ("keep_slabs", ctypes.c_int32)]
+
+
+class hydro_serve_stats_t(ctypes.Structure):
+    _fields_ = [("agg", hydro_agg_stats_t), ("makespan_us", ctypes.c_double),
+                ("first_admit_us", ctypes.c_double), ("max_live", ctypes.c_uint64),
+                ("slab_waits", ctypes.c_uint64)]
+
 _lib = None
 
 
@@ -62,6 +88,25 @@ def lib() -> ctypes.CDLL:
             f.restype = ctypes.c_int
         L.hydro_plan_destroy.argtypes = [ctypes.c_void_p]
         L.hydro_plan_destroy.restype = ctypes.c_int
+        AP = ctypes.c_void_p
+        L.hydro_agg_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_double,
+                                       ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32]
+        L.hydro_submit.argtypes = [AP, P, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]
+        L.hydro_flush.argtypes = [AP]
+        L.hydro_progress.argtypes = [AP]
+        L.hydro_poll.argtypes = [AP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_double)]
+        L.hydro_wait.argtypes = [AP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+        L.hydro_agg_stats.argtypes = [AP, ctypes.POINTER(hydro_agg_stats_t)]
+        L.hydro_agg_destroy.argtypes = [AP]
+        L.hydro_serve_run.argtypes = [ctypes.POINTER(hydro_serve_config_t), P, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.POINTER(hydro_serve_stats_t)]
+        for name in ("hydro_agg_create", "hydro_submit", "hydro_flush", "hydro_progress",
+                     "hydro_poll", "hydro_wait", "hydro_agg_stats", "hydro_agg_destroy",
+                     "hydro_serve_run"):
+            getattr(L, name).restype = ctypes.c_int
         L.hydro_last_error.argtypes = []
         L.hydro_last_error.restype = ctypes.c_char_p
         L.hydro_version.argtypes = []
@@ -173,3 +218,98 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class Aggregator:
+    """Submit/flush aggregation of sub-grid tasks (hydro_agg_*)."""
+
+    def __init__(self, max_width: int, timeout_us: float = 50.0, n_streams: int = 2,
+                 hbm_budget_bytes: int = 0, flush_when_idle: bool = True):
+        h = ctypes.c_void_p()
+        _check(lib().hydro_agg_create(ctypes.byref(h), int(max_width), float(timeout_us),
+                                      int(n_streams), int(hbm_budget_bytes), int(bool(flush_when_idle))))
+        self._h = h
+
+    def submit(self, desc, dt: float, dx: float) -> int:
+        """desc: a hydro_subgrid_t (or a 1-element descriptor array).  Returns
+        the ticket; raises HydroError (code HYDRO_EAGAIN when admission is
+        refused)."""
+        t = ctypes.c_uint64()
+        d = desc if isinstance(desc, hydro_subgrid_t) else desc[0]
+        _check(lib().hydro_submit(self._h, ctypes.byref(d), float(dt), float(dx), ctypes.byref(t)))
+        return int(t.value)
+
+    def try_submit(self, desc, dt: float, dx: float):
+        """Like submit, but returns None instead of raising on HYDRO_EAGAIN."""
+        t = ctypes.c_uint64()
+        d = desc if isinstance(desc, hydro_subgrid_t) else desc[0]
+        rc = lib().hydro_submit(self._h, ctypes.byref(d), float(dt), float(dx), ctypes.byref(t))
+        if rc == HYDRO_EAGAIN:
+            return None
+        _check(rc)
+        return int(t.value)
+
+    def flush(self) -> None:
+        _check(lib().hydro_flush(self._h))
+
+    def progress(self) -> None:
+        _check(lib().hydro_progress(self._h))
+
+    def poll(self, ticket: int):
+        """(done, amax) without blocking; amax is None until done."""
+        done = ctypes.c_int32()
+        am = ctypes.c_double()
+        _check(lib().hydro_poll(self._h, int(ticket), ctypes.byref(done), ctypes.byref(am)))
+        return (True, am.value) if done.value else (False, None)
+
+    def wait(self, ticket: int) -> float:
+        am = ctypes.c_double()
+        _check(lib().hydro_wait(self._h, int(ticket), ctypes.byref(am)))
+        return am.value
+
+    def stats(self) -> dict:
+        s = hydro_agg_stats_t()
+        _check(lib().hydro_agg_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self) -> None:
+        if self._h:
+            h, self._h = self._h, None
+            _check(lib().hydro_agg_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def serve_run(pool_descs, task_subgrid, arrival_us, *, nfields, dt, dx, slab_arenas,
+              max_width=64, timeout_us=50.0, n_streams=2, flush_when_idle=True,
+              keep_slabs=False, want_slabs=False):
+    """Run the serving loop (hydro_serve_run).  slab_arenas: three (tensor or
+    None, nslabs) pairs for n = 8, 12, 16.  Returns (latency_us, amax, slabs,
+    stats) as numpy arrays / dict."""
+    import numpy as np
+    arr, count = pool_descs
+    task_subgrid = np.ascontiguousarray(task_subgrid, dtype=np.int32)
+    arrival_us = np.ascontiguousarray(arrival_us, dtype=np.float64)
+    n = int(task_subgrid.shape[0])
+    cfg = hydro_serve_config_t()
+    cfg.max_width, cfg.timeout_us, cfg.n_streams = int(max_width), float(timeout_us), int(n_streams)
+    cfg.flush_when_idle, cfg.nfields = int(bool(flush_when_idle)), int(nfields)
+    cfg.dt, cfg.dx, cfg.keep_slabs = float(dt), float(dx), int(bool(keep_slabs))
+    for e, (t, k) in enumerate(slab_arenas):
+        cfg.slab_base[e] = _ptr(t) if t is not None else 0
+        cfg.slabs[e] = int(k)
+    lat = np.zeros(n, dtype=np.float64)
+    am = np.zeros(n, dtype=np.float64)
+    slabs = np.zeros(n, dtype=np.uint64) if want_slabs else None
+    st = hydro_serve_stats_t()
+    _check(lib().hydro_serve_run(ctypes.byref(cfg), arr, count, task_subgrid.ctypes.data,
+                                 arrival_us.ctypes.data, n, lat.ctypes.data, am.ctypes.data,
+                                 slabs.ctypes.data if want_slabs else None, ctypes.byref(st)))
+    stats = {"agg": st.agg.as_dict(), "makespan_us": st.makespan_us,
+             "first_admit_us": st.first_admit_us, "max_live": int(st.max_live),
+             "slab_waits": int(st.slab_waits)}
+    return lat, am, slabs, stats

@@ -1,0 +1,181 @@
+"""Aggregator and serving loop on the GPU.  Every task's result must be
+bitwise identical to the same sub-grid stepped alone by hydro_step, whatever
+batch, width, stream or admission order it ran in (batch independence)."""
+import numpy as np
+import pytest
+
+from paper_2210_06438_amd import hydroagg, workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def alone(U, dt, dx, levels=None):
+    """Reference: hydro_step on each sub-grid separately."""
+    outs, amaxs = [], []
+    for i in range(U.shape[0]):
+        u_in = torch.from_numpy(np.ascontiguousarray(U[i:i + 1])).cuda()
+        u_out = u_in.clone()
+        am = torch.zeros(1, dtype=torch.float64, device="cuda")
+        hydroagg.hydro_step(hydroagg.subgrids(u_in, u_out, levels=None if levels is None else [levels[i]]),
+                            dt, dx, am)
+        torch.cuda.synchronize()
+        outs.append(u_out.cpu().numpy()[0])
+        amaxs.append(float(am.cpu()[0]))
+    return outs, amaxs
+
+
+@pytest.mark.parametrize("width,streams,idle", [(1, 1, False), (4, 2, True), (64, 2, True), (5, 1, False)])
+def test_aggregator_results_match_alone(dev, width, streams, idle):
+    print(f"agg: width={width} streams={streams} idle={idle}", flush=True)
+    U8 = workloads.random_smooth(9, n=8, nfields=11, seed=600)
+    U12 = workloads.random_smooth(4, n=12, nfields=11, seed=601)
+    dt, dx = 0.002, 0.05
+    r8, a8 = alone(U8, dt, dx)
+    r12, a12 = alone(U12, dt, dx)
+    u8 = torch.from_numpy(U8).to(dev)
+    u12 = torch.from_numpy(U12).to(dev)
+    o8, o12 = u8.clone(), u12.clone()
+    d8, _ = hydroagg.subgrids(u8, o8)
+    d12, _ = hydroagg.subgrids(u12, o12)
+    agg = hydroagg.Aggregator(width, timeout_us=-1.0, n_streams=streams, flush_when_idle=idle)
+    tickets = []
+    order = [("8", i) for i in range(9)] + [("12", i) for i in range(4)]
+    np.random.default_rng(width).shuffle(order)
+    for kind, i in order:
+        tickets.append((kind, i, agg.submit((d8 if kind == "8" else d12)[i], dt, dx)))
+    agg.flush()
+    got = {}
+    for kind, i, t in tickets:
+        got[(kind, i)] = agg.wait(t)
+    st = agg.stats()
+    agg.close()
+    torch.cuda.synchronize()
+    assert st["launched"] == 13 and st["submitted"] == 13
+    if width == 1:
+        assert st["batches"] == 13
+    O8, O12 = o8.cpu().numpy(), o12.cpu().numpy()
+    for i in range(9):
+        assert np.array_equal(O8[i], r8[i]) and got[("8", i)] == a8[i]
+    for i in range(4):
+        assert np.array_equal(O12[i], r12[i]) and got[("12", i)] == a12[i]
+
+
+def test_aggregator_byte_budget(dev):
+    U = workloads.random_smooth(10, n=8, nfields=6, seed=610)
+    dt, dx = 0.002, 0.05
+    ref, ref_a = alone(U, dt, dx)
+    u = torch.from_numpy(U).to(dev)
+    o = u.clone()
+    d, _ = hydroagg.subgrids(u, o)
+    per = U[0].nbytes
+    agg = hydroagg.Aggregator(2, timeout_us=-1.0, n_streams=1, hbm_budget_bytes=3 * per,
+                              flush_when_idle=False)
+    tickets, refused = [], 0
+    for i in range(10):
+        while True:
+            t = agg.try_submit(d[i], dt, dx)
+            if t is not None:
+                tickets.append(t)
+                break
+            refused += 1
+            agg.flush()
+            agg.progress()
+    amax = [agg.wait(t) for t in tickets]
+    st = agg.stats()
+    agg.close()
+    torch.cuda.synchronize()
+    assert refused > 0 and st["refused"] == refused
+    assert np.array_equal(o.cpu().numpy(), np.stack(ref)) and amax == ref_a
+
+
+def test_aggregator_errors(dev):
+    with pytest.raises(hydroagg.HydroError):
+        hydroagg.Aggregator(0)
+    with pytest.raises(hydroagg.HydroError):
+        hydroagg.Aggregator(4, n_streams=9)
+    agg = hydroagg.Aggregator(4)
+    with pytest.raises(hydroagg.HydroError):
+        agg.poll(12345)
+    with pytest.raises(hydroagg.HydroError):
+        agg.wait(12345)
+    agg.close()
+
+
+def _pool(dev, count=24, seed=620):
+    groups = workloads.polytrope(count=count, seed=seed)
+    tensors, descs, host = [], [], []
+    for N, levels, U, _ in groups:
+        t = torch.from_numpy(U).to(dev)
+        tensors.append(t)
+        descs.append(hydroagg.subgrids(t, t.clone(), levels=levels))
+        host.append((N, levels, U))
+    pool = hydroagg.concat(*descs)
+    # flatten the host side in the same order
+    Us, Ls, Ns = [], [], []
+    for N, levels, U in host:
+        for i in range(U.shape[0]):
+            Us.append(U[i])
+            Ls.append(int(levels[i]))
+            Ns.append(N)
+    return pool, tensors, Us, Ls, Ns
+
+
+def test_serving_loop_results_match_alone(dev):
+    pool, keep, Us, Ls, Ns = _pool(dev)
+    rng = np.random.default_rng(7)
+    ntask = 90
+    task = rng.integers(0, len(Us), ntask).astype(np.int32)
+    arrival = np.cumsum(rng.exponential(50.0, ntask))          # 20k tasks/s
+    dx = 0.5
+    dt = 1e-4
+    sizes = {8: 14 ** 3, 12: 18 ** 3, 16: 22 ** 3}
+    counts = {N: int(np.sum(np.array([Ns[s] for s in task]) == N)) for N in (8, 12, 16)}
+    arenas = []
+    for N in (8, 12, 16):
+        k = counts[N]
+        arenas.append((torch.zeros(max(k, 1) * 11 * sizes[N], dtype=torch.float64, device=dev), k))
+    lat, am, slabs, st = hydroagg.serve_run(pool, task, arrival, nfields=11, dt=dt, dx=dx,
+                                            slab_arenas=arenas, max_width=16, timeout_us=50.0,
+                                            n_streams=2, keep_slabs=True, want_slabs=True)
+    torch.cuda.synchronize()
+    assert st["agg"]["launched"] == ntask and np.all(lat > 0)
+    # compare each task's slab with the sub-grid stepped alone
+    base = {N: arenas[e][0].data_ptr() for e, N in enumerate((8, 12, 16))}
+    arena_host = {N: arenas[e][0].cpu().numpy() for e, N in enumerate((8, 12, 16))}
+    checked = 0
+    for i in range(ntask):
+        s = int(task[i])
+        N = Ns[s]
+        M = N + 6
+        off = (int(slabs[i]) - base[N]) // 8
+        out = arena_host[N][off:off + 11 * M ** 3].reshape(11, M, M, M)
+        ref, ref_a = alone(Us[s][None], dt, dx, levels=[Ls[s]])
+        inner = (slice(None), slice(3, 3 + N), slice(3, 3 + N), slice(3, 3 + N))
+        assert np.array_equal(out[inner], ref[0][inner]), i
+        assert am[i] == ref_a[0]
+        checked += 1
+    assert checked == ntask
+
+
+def test_serving_loop_admission_bound(dev):
+    pool, keep, Us, Ls, Ns = _pool(dev, count=16, seed=630)
+    rng = np.random.default_rng(8)
+    ntask = 600
+    task = rng.integers(0, len(Us), ntask).astype(np.int32)
+    arrival = np.cumsum(rng.exponential(5.0, ntask))            # 200k tasks/s: overload
+    sizes = {8: 14 ** 3, 12: 18 ** 3, 16: 22 ** 3}
+    arenas = [(torch.zeros(4 * 11 * sizes[N], dtype=torch.float64, device=dev), 4) for N in (8, 12, 16)]
+    lat, am, _, st = hydroagg.serve_run(pool, task, arrival, nfields=11, dt=1e-4, dx=0.5,
+                                        slab_arenas=arenas, max_width=8, timeout_us=50.0,
+                                        n_streams=2)
+    torch.cuda.synchronize()
+    assert st["agg"]["launched"] == ntask and st["max_live"] <= 12
+    assert st["slab_waits"] > 0 and np.all(lat > 0) and np.all(am > 0)
