@@ -57,6 +57,108 @@ def measured_traffic(version, workload):
     return int(rec["traffic_bytes_per_launch"])
 
 
+def uneven_leg(args, torch, hydroagg, workloads, dev, stream):
+    """3000 sub-grids of mixed edges (polytrope), one hipGraph launch per step."""
+    dx = 0.5
+    log("uneven: generating 3000 polytrope sub-grids")
+    groups = workloads.polytrope(count=args.uneven_count, seed=3)
+    tensors, descs, cells, tile_bytes = [], [], 0, 0
+    for N, levels, U, _ in groups:
+        t_in = torch.from_numpy(U).to(dev)
+        t_out = t_in.clone()
+        tensors.append((N, levels, t_in, t_out))
+        descs.append(hydroagg.subgrids(t_in, t_out, levels=levels))
+        cells += U.shape[0] * N ** 3
+        tile_bytes += U.shape[0] * bytes_per_subgrid(N, U.shape[1])[1]
+    batch = hydroagg.concat(*descs)
+    count = batch[1]
+    amax = torch.zeros(count, dtype=torch.float64, device=dev)
+    plan = hydroagg.Plan(batch)
+    plan.step(0.0, dx, amax, stream)
+    torch.cuda.synchronize()
+    lv = torch.cat([torch.as_tensor(l, dtype=torch.float64) for _, l, _, _ in tensors]).to(dev)
+    dt = float(0.4 * torch.min(dx * torch.pow(2.0, -lv) / amax))
+    for _ in range(3):
+        plan.graph(dt, dx, amax, stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.uneven_steps):
+        plan.graph(dt, dx, amax, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.uneven_steps
+    e0.record(stream)
+    hydroagg.hydro_step_each(batch, dt, dx, amax, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    each_ms = e0.elapsed_time(e1)
+    plan.close()
+    mix = {int(N): int(t.shape[0]) for N, _, t, _ in tensors}
+    log(f"uneven: {ms * 1e3:.1f} us/step, {cells / ms / 1e6:.3f} G cell-updates/s; "
+        f"per-sub-grid launches {each_ms:.1f} ms")
+    res = {
+        "workload": f"{count} polytrope sub-grids, edges {mix}, 11 FP64 fields, random octree "
+                    "levels 2-5, one hipGraph launch per step",
+        "value": round(cells / (ms * 1e-3), 1), "unit": "cell-updates/s",
+        "ms_per_step": round(ms, 5), "cells": cells,
+        "achieved_gbs": round(tile_bytes / (ms * 1e-3) / 1e9, 1),
+        "frac": round(tile_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "per_subgrid_launch": {"ms_per_step": round(each_ms, 3),
+                               "value": round(cells / (each_ms * 1e-3), 1)},
+        "aggregation_speedup": round(each_ms / ms, 2),
+    }
+    return res, tensors, dt, dx
+
+
+def serving_leg(args, torch, hydroagg, np, tensors, dt, dx, dev):
+    """Poisson arrivals of single-sub-grid tasks on the resident uneven pool;
+    admission bounded by a fixed HBM budget of output slabs."""
+    descs = [hydroagg.subgrids(t_in, t_out, levels=levels) for _, levels, t_in, t_out in tensors]
+    pool = hydroagg.concat(*descs)
+    edges = np.concatenate([np.full(t.shape[0], N) for N, _, t, _ in tensors])
+    cells_of = edges.astype(np.int64) ** 3
+    nfields = int(tensors[0][2].shape[1])
+    size = {N: nfields * (N + 6) ** 3 * 8 for N in (8, 12, 16)}
+    share = {N: float(np.sum(edges == N)) * size[N] for N in (8, 12, 16)}
+    tot = sum(share.values())
+    budget = args.serve_budget_mb * 2 ** 20
+    arenas = []
+    for N in (8, 12, 16):
+        k = max(int(budget * share[N] / tot // size[N]), 1 if share[N] else 0)
+        arenas.append((torch.zeros(max(k, 1) * size[N] // 8, dtype=torch.float64, device=dev), k))
+    used = sum(k * size[N] for (t, k), N in zip(arenas, (8, 12, 16)))
+    out = {"pool": int(len(edges)), "hbm_budget_bytes": int(used),
+           "slabs": {N: k for (t, k), N in zip(arenas, (8, 12, 16))},
+           "width": args.serve_width, "timeout_us": 50.0, "streams": args.serve_streams,
+           "runs": []}
+    rng = np.random.Generator(np.random.PCG64(4))
+    for rate in args.serve_rates:
+        n = int(rate * args.serve_seconds)
+        task = rng.integers(0, len(edges), n).astype(np.int32)
+        arrival = np.cumsum(rng.exponential(1e6 / rate, n))
+        for label, width in (("aggregated", args.serve_width), ("per_task_launch", 1)):
+            lat, am, _, st = hydroagg.serve_run(
+                pool, task, arrival, nfields=nfields, dt=dt, dx=dx, slab_arenas=arenas,
+                max_width=width, timeout_us=50.0, n_streams=args.serve_streams,
+                flush_when_idle=True)
+            span = st["makespan_us"] * 1e-6
+            rec = {"mode": label, "rate_per_s": rate, "tasks": n, "width": width,
+                   "p50_us": round(float(np.percentile(lat, 50)), 1),
+                   "p99_us": round(float(np.percentile(lat, 99)), 1),
+                   "mean_us": round(float(lat.mean()), 1),
+                   "throughput_tasks_s": round(n / span, 1),
+                   "cell_updates_s": round(float(cells_of[task].sum()) / span, 1),
+                   "batches": st["agg"]["batches"],
+                   "mean_batch": round(n / max(st["agg"]["batches"], 1), 2),
+                   "max_live": st["max_live"]}
+            out["runs"].append(rec)
+            log(f"serving {label} at {rate}/s: p50 {rec['p50_us']} us, p99 {rec['p99_us']} us, "
+                f"{rec['throughput_tasks_s']:.0f} tasks/s, mean batch {rec['mean_batch']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +175,15 @@ def main():
     ap.add_argument("--copy-reps", type=int, default=10,
                     help="timed repetitions of a plain device copy of the input buffer")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-size leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--uneven-count", type=int, default=3000)
+    ap.add_argument("--uneven-steps", type=int, default=20)
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=[20000.0, 200000.0])
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--serve-width", type=int, default=64)
+    ap.add_argument("--serve-streams", type=int, default=2)
+    ap.add_argument("--serve-budget-mb", type=float, default=64.0)
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads (0 = OMP_NUM_THREADS or all cores)")
     args = ap.parse_args()
@@ -195,6 +306,16 @@ def main():
                          "OpenMP over sub-grids"}
         log(f"cpu baseline {cells / med / 1e6:.2f} M cell-updates/s")
 
+    uneven = serving = None
+    if not args.no_uneven or not args.no_serving:
+        del u_in, u_out
+        torch.cuda.empty_cache()
+        uneven, tensors, udt, udx = uneven_leg(args, torch, hydroagg, workloads, dev, stream)
+        if args.no_uneven:
+            uneven = None
+        if not args.no_serving:
+            serving = serving_leg(args, torch, hydroagg, np, tensors, udt, udx, dev)
+
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -219,6 +340,8 @@ def main():
         "aggregation_speedup": None if each_ms is None else round(each_ms / ms, 2),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "uneven": uneven,
+        "serving": serving,
     }
     plan.close()
     print(json.dumps(out), flush=True)

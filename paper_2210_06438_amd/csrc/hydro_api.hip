@@ -55,27 +55,6 @@ namespace {
       return fail(HYDRO_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-// Work-groups per CU the 8^3 kernel is built for (LDS and registers allow
-// two resident work-groups of 192 lanes).
-constexpr int kLds8WgPerCu = 2;
-
-int g_cu_count[16] = {0};
-
-// Persistent grid for `n` sub-grids of the 8^3 kernel on the current device.
-int lds8_grid(int n) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) dev = 0;
-  if (g_cu_count[dev] == 0) {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
-    g_cu_count[dev] = cus;
-  }
-  (void)kLds8WgPerCu;
-  return n;   // one work-group per sub-grid
-}
-
 // Shape classes: (n, nfields) -> index.
 constexpr int kEdges[3] = {8, 12, 16};
 constexpr int kFields[2] = {6, 11};
@@ -147,16 +126,25 @@ int validate(const hydro_subgrid_t* sg, int32_t count, double dt, double dx) {
   return HYDRO_OK;
 }
 
+// Grid of the block kernel for n sub-grids of edge N.
+template <int N>
+int block_grid(int n) {
+  constexpr int B = hydro::Blocks<N + 6>::kPerSubgrid;
+  return B == 1 ? n : ((n + 7) / 8) * 8 * B;
+}
+
 template <int N, int F>
 int launch_table(const DevDesc* table, int n, double dt, double dx, double* amax,
                  hipStream_t stream) {
   if (n <= 0) return HYDRO_OK;
-  if constexpr (N == 8)
-    hipLaunchKernelGGL((hydro::hydro_lds8_kernel<F>), dim3(lds8_grid(n)),
-                       dim3(hydro::Lds8::kThreads), 0, stream, table, n, dt, dx, amax);
-  else
-    hipLaunchKernelGGL((hydro::hydro_table_kernel<N, F>), dim3(n),
-                       dim3(hydro::Shape<N>::kThreads), 0, stream, table, dt, dx, amax);
+  constexpr int B = hydro::Blocks<N + 6>::kPerSubgrid;
+  if (B > 1 && amax) {
+    hipLaunchKernelGGL(hydro::amax_zero_table, dim3((n + 255) / 256), dim3(256), 0, stream,
+                       table, n, amax);
+    HIP_TRY(hipGetLastError());
+  }
+  hipLaunchKernelGGL((hydro::hydro_lds8_kernel<F, N + 6>), dim3(block_grid<N>(n)),
+                     dim3(hydro::Lds8::kThreads), 0, stream, table, n, dt, dx, amax);
   HIP_TRY(hipGetLastError());
   return HYDRO_OK;
 }
@@ -165,12 +153,13 @@ template <int N, int F>
 int launch_args(const ArgDescs& a, int n, double dt, double dx, double* amax,
                 hipStream_t stream) {
   if (n <= 0) return HYDRO_OK;
-  if constexpr (N == 8)
-    hipLaunchKernelGGL((hydro::hydro_lds8_arg_kernel<F>), dim3(n),
-                       dim3(hydro::Lds8::kThreads), 0, stream, a, dt, dx, amax);
-  else
-    hipLaunchKernelGGL((hydro::hydro_arg_kernel<N, F>), dim3(n),
-                       dim3(hydro::Shape<N>::kThreads), 0, stream, a, dt, dx, amax);
+  constexpr int B = hydro::Blocks<N + 6>::kPerSubgrid;
+  if (B > 1 && amax) {
+    hipLaunchKernelGGL(hydro::amax_zero_args, dim3(1), dim3(64), 0, stream, a, n, amax);
+    HIP_TRY(hipGetLastError());
+  }
+  hipLaunchKernelGGL((hydro::hydro_lds8_arg_kernel<F, N + 6>), dim3(n * B),
+                     dim3(hydro::Lds8::kThreads), 0, stream, a, dt, dx, amax);
   HIP_TRY(hipGetLastError());
   return HYDRO_OK;
 }
@@ -201,26 +190,6 @@ int dispatch_args(int cls, const ArgDescs& a, int n, double dt, double dx,
   return fail(HYDRO_EINVAL, "bad class");
 }
 
-
-const void* table_kernel_fn(int cls) {
-  switch (cls) {
-    case 0: return (const void*)hydro::hydro_lds8_kernel<6>;
-    case 1: return (const void*)hydro::hydro_lds8_kernel<11>;
-    case 2: return (const void*)hydro::hydro_table_kernel<12, 6>;
-    case 3: return (const void*)hydro::hydro_table_kernel<12, 11>;
-    case 4: return (const void*)hydro::hydro_table_kernel<16, 6>;
-    case 5: return (const void*)hydro::hydro_table_kernel<16, 11>;
-  }
-  return nullptr;
-}
-
-int threads_of_class(int cls) {
-  switch (cls / 2) {
-    case 0: return hydro::Lds8::kThreads;
-    case 1: return hydro::Shape<12>::kThreads;
-    default: return hydro::Shape<16>::kThreads;
-  }
-}
 
 DevDesc to_dev(const hydro_subgrid_t& s, int index) {
   DevDesc d;
@@ -306,47 +275,23 @@ struct hydro_plan {
   int count = 0;
   int off[kClasses] = {0};
   int num[kClasses] = {0};
-  // graph state
+  // graph of one step, captured on a private stream for given (dt, dx, amax)
+  hipStream_t capture = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipGraphNode_t node[kClasses] = {nullptr};
-  struct Args {
-    const DevDesc* table;
-    int count;
-    double dt, dx;
-    double* amax;
-    void* ptrs[5];
-  } args[kClasses];
+  double g_dt = -1.0, g_dx = -1.0;
+  double* g_amax = nullptr;
 };
 
 namespace {
 
-void plan_set_args(hydro_plan* p, int c, double dt, double dx, double* amax) {
-  auto& a = p->args[c];
-  a.table = p->table + p->off[c];
-  a.dt = dt;
-  a.dx = dx;
-  a.amax = amax;
-  a.count = p->num[c];
-  // the 8^3 kernels (classes 0, 1) also take the sub-grid count
-  int k = 0;
-  a.ptrs[k++] = &a.table;
-  if (c < 2) a.ptrs[k++] = &a.count;
-  a.ptrs[k++] = &a.dt;
-  a.ptrs[k++] = &a.dx;
-  a.ptrs[k++] = &a.amax;
-}
-
-hipKernelNodeParams plan_node_params(hydro_plan* p, int c) {
-  hipKernelNodeParams kp;
-  memset(&kp, 0, sizeof kp);
-  kp.func = const_cast<void*>(table_kernel_fn(c));
-  kp.gridDim = dim3(c < 2 ? lds8_grid(p->num[c]) : p->num[c]);
-  kp.blockDim = dim3(threads_of_class(c));
-  kp.sharedMemBytes = 0;
-  kp.kernelParams = p->args[c].ptrs;
-  kp.extra = nullptr;
-  return kp;
+int plan_launches(hydro_plan* p, double dt, double dx, double* amax, hipStream_t s) {
+  for (int c = 0; c < kClasses; ++c) {
+    if (!p->num[c]) continue;
+    int rc = dispatch_table(c, p->table + p->off[c], p->num[c], dt, dx, amax, s);
+    if (rc) return rc;
+  }
+  return HYDRO_OK;
 }
 
 }  // namespace
@@ -407,6 +352,13 @@ int hydro_plan_create(hydro_plan_t** out, const hydro_subgrid_t* sg, int32_t cou
   int fill[kClasses];
   memcpy(fill, p->off, sizeof fill);
   for (int i = 0; i < count; ++i) host[fill[class_of(sg[i].n, sg[i].nfields)]++] = to_dev(sg[i], i);
+  {
+    hipError_t e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete p;
+      return fail(HYDRO_EHIP, "hipStreamCreate(plan): %s", hipGetErrorString(e));
+    }
+  }
   if (count > 0) {
     hipError_t e = hipMalloc((void**)&p->table, sizeof(DevDesc) * count);
     if (e != hipSuccess) {
@@ -429,12 +381,7 @@ int hydro_plan_step(hydro_plan_t* p, double dt, double dx, double* amax_dev, voi
   if (!p) return fail(HYDRO_EINVAL, "plan is NULL");
   int rc = validate(nullptr, 0, dt, dx);
   if (rc) return rc;
-  for (int c = 0; c < kClasses; ++c) {
-    if (!p->num[c]) continue;
-    rc = dispatch_table(c, p->table + p->off[c], p->num[c], dt, dx, amax_dev, (hipStream_t)stream);
-    if (rc) return rc;
-  }
-  return HYDRO_OK;
+  return plan_launches(p, dt, dx, amax_dev, (hipStream_t)stream);
 }
 
 int hydro_plan_launch_graph(hydro_plan_t* p, double dt, double dx, double* amax_dev, void* stream) {
@@ -443,24 +390,30 @@ int hydro_plan_launch_graph(hydro_plan_t* p, double dt, double dx, double* amax_
   int rc = validate(nullptr, 0, dt, dx);
   if (rc) return rc;
   if (p->count == 0) return HYDRO_OK;
-  if (!p->exec) {
-    HIP_TRY(hipGraphCreate(&p->graph, 0));
-    for (int c = 0; c < kClasses; ++c) {
-      if (!p->num[c]) continue;
-      plan_set_args(p, c, dt, dx, amax_dev);
-      hipKernelNodeParams kp = plan_node_params(p, c);
-      HIP_TRY(hipGraphAddKernelNode(&p->node[c], p->graph, nullptr, 0, &kp));
+  if (!p->exec || p->g_dt != dt || p->g_dx != dx || p->g_amax != amax_dev) {
+    // (re)capture one step on the plan's private stream
+    if (p->exec) {
+      (void)hipGraphExecDestroy(p->exec);
+      p->exec = nullptr;
     }
+    if (p->graph) {
+      (void)hipGraphDestroy(p->graph);
+      p->graph = nullptr;
+    }
+    HIP_TRY(hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal));
+    rc = plan_launches(p, dt, dx, amax_dev, p->capture);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->capture, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(HYDRO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    p->graph = g;
     HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
-  } else {
-    for (int c = 0; c < kClasses; ++c) {
-      if (!p->num[c]) continue;
-      auto& a = p->args[c];
-      if (a.dt == dt && a.dx == dx && a.amax == amax_dev) continue;
-      plan_set_args(p, c, dt, dx, amax_dev);
-      hipKernelNodeParams kp = plan_node_params(p, c);
-      HIP_TRY(hipGraphExecKernelNodeSetParams(p->exec, p->node[c], &kp));
-    }
+    p->g_dt = dt;
+    p->g_dx = dx;
+    p->g_amax = amax_dev;
   }
   HIP_TRY(hipGraphLaunch(p->exec, (hipStream_t)stream));
   return HYDRO_OK;
@@ -474,6 +427,7 @@ int hydro_plan_destroy(hydro_plan_t* p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->table) (void)hipFree(p->table);
+  if (p->capture) (void)hipStreamDestroy(p->capture);
   delete p;
   return rc;
 }
