@@ -112,7 +112,33 @@ def uneven_leg(args, torch, hydroagg, workloads, dev, stream):
     return res, tensors, dt, dx
 
 
-def serving_leg(args, torch, hydroagg, np, tensors, dt, dx, dev):
+def learned_leg(args, dev):
+    """Width cost model trained on the GPU on the stored sweeps: held-out
+    regret against the exhaustive tuner and the best static width."""
+    from paper_2210_06438_amd import learned
+    out = {"splits": args.learned_splits, "epochs": 2000, "features": 5,
+           "overload_clip_us": learned.OVERLOAD_US,
+           "exhaustive_runs_per_condition": len(learned.WIDTHS), "model_runs_per_condition": 0}
+    for name in ("timeout", "idle"):
+        recs = learned.load_sweep(name)
+        t0 = time.time()
+        cv = learned.cross_validate(recs, splits=range(args.learned_splits), device=dev)
+        sec = time.time() - t0
+        out[name] = {"policy": ("launch on width or 50 us timeout" if name == "timeout"
+                                else "launch on width, 50 us timeout or idle stream"),
+                     "model_mean_regret": round(cv["mlp_mean_regret"], 4),
+                     "static_mean_regret": round(cv["static_mean_regret"], 4),
+                     "static_widths": sorted({e["static_width"] for e in cv["splits"]}),
+                     "model_wins": cv["mlp_wins"],
+                     "train_seconds_per_model": round(sec / args.learned_splits, 3)}
+        log(f"learned width ({name}): model regret {cv['mlp_mean_regret']:.3f} vs best static "
+            f"{cv['static_mean_regret']:.3f}, wins {cv['mlp_wins']}/{args.learned_splits}, "
+            f"{sec / args.learned_splits:.2f} s per model")
+    model = learned.WidthModel(device=dev).fit(learned.load_sweep("timeout"))
+    return out, model
+
+
+def serving_leg(args, torch, hydroagg, np, tensors, dt, dx, dev, model=None):
     """Poisson arrivals of single-sub-grid tasks on the resident uneven pool;
     admission bounded by a fixed HBM budget of output slabs."""
     descs = [hydroagg.subgrids(t_in, t_out, levels=levels) for _, levels, t_in, t_out in tensors]
@@ -138,13 +164,19 @@ def serving_leg(args, torch, hydroagg, np, tensors, dt, dx, dev):
         n = int(rate * args.serve_seconds)
         task = rng.integers(0, len(edges), n).astype(np.int32)
         arrival = np.cumsum(rng.exponential(1e6 / rate, n))
-        for label, width in (("aggregated", args.serve_width), ("per_task_launch", 1)):
+        modes = [("aggregated", args.serve_width, True), ("per_task_launch", 1, True)]
+        if model is not None:
+            mix = {int(N): float(np.mean(edges == N)) for N in (8, 12, 16)}
+            modes.append(("timeout_policy_learned_width",
+                          model.choose_mix(mix, nfields, rate), False))
+        for label, width, idle in modes:
             lat, am, _, st = hydroagg.serve_run(
                 pool, task, arrival, nfields=nfields, dt=dt, dx=dx, slab_arenas=arenas,
                 max_width=width, timeout_us=50.0, n_streams=args.serve_streams,
-                flush_when_idle=True)
+                flush_when_idle=idle)
             span = st["makespan_us"] * 1e-6
             rec = {"mode": label, "rate_per_s": rate, "tasks": n, "width": width,
+                   "flush_when_idle": idle,
                    "p50_us": round(float(np.percentile(lat, 50)), 1),
                    "p99_us": round(float(np.percentile(lat, 99)), 1),
                    "mean_us": round(float(lat.mean()), 1),
@@ -184,6 +216,8 @@ def main():
     ap.add_argument("--serve-width", type=int, default=64)
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--serve-budget-mb", type=float, default=64.0)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-width leg")
+    ap.add_argument("--learned-splits", type=int, default=10)
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads (0 = OMP_NUM_THREADS or all cores)")
     args = ap.parse_args()
@@ -276,7 +310,7 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": measured_traffic(version, workload_name),
-        "kernel": (f"hydro_lds8_kernel<{nf}>" if n == 8 else f"hydro_table_kernel<{n},{nf}>"),
+        "kernel": f"hydro_lds8_kernel<{nf},{n + 2 * GHOST}>",
         "kernel_version": version,
         "algorithmic_bytes_per_launch": tile_b * count,
         "bytes_definition": "stored (n+6)^3 tile read once + interior n^3 written once, 8 B x F per cell",
@@ -306,6 +340,10 @@ def main():
                          "OpenMP over sub-grids"}
         log(f"cpu baseline {cells / med / 1e6:.2f} M cell-updates/s")
 
+    learned_res = model = None
+    if not args.no_learned:
+        learned_res, model = learned_leg(args, dev)
+
     uneven = serving = None
     if not args.no_uneven or not args.no_serving:
         del u_in, u_out
@@ -314,7 +352,7 @@ def main():
         if args.no_uneven:
             uneven = None
         if not args.no_serving:
-            serving = serving_leg(args, torch, hydroagg, np, tensors, udt, udx, dev)
+            serving = serving_leg(args, torch, hydroagg, np, tensors, udt, udx, dev, model)
 
     out = {
         "metric": METRIC,
@@ -342,6 +380,7 @@ def main():
         "cpu_baseline": cpu,
         "uneven": uneven,
         "serving": serving,
+        "learned_width": learned_res,
     }
     plan.close()
     print(json.dumps(out), flush=True)

@@ -191,6 +191,35 @@ int hydro_serve_run(const hydro_serve_config_t *cfg, const hydro_subgrid_t *pool
                     const double *arrival_us, int32_t ntasks, double *latency_us,
                     double *amax_out, double **out_slab, hydro_serve_stats_t *stats);
 
+/*
+ * Width cost model: a 5-64-64-1 FP32 perceptron with ReLU that predicts the
+ * (standardised, log) p99 latency of a serving condition at an aggregation
+ * width, trained on the GPU by these kernels; the width with the lowest
+ * prediction is chosen (it replaces hand-sweeping the paper's "max aggregated
+ * kernels" parameter, Section VI-B).  All pointers are device pointers.
+ * params: HYDRO_MLP_PARAMS floats laid out W1[64][5] b1[64] W2[64][64] b2[64]
+ * W3[64] b3.  x: rows x 5 features, row-major.  act: 2 x rows x 64 floats
+ * (hidden activations, written by the forward pass when not NULL and needed
+ * by the backward pass).  scratch: 2 x rows x 64 floats.  grad: HYDRO_MLP_
+ * PARAMS floats (overwritten, not accumulated).  Reductions run in a fixed
+ * order: results are deterministic.  Nothing is allocated.
+ */
+#define HYDRO_MLP_INPUTS 5
+#define HYDRO_MLP_HIDDEN 64
+#define HYDRO_MLP_PARAMS 4609
+int hydro_mlp_forward(const float *params, const float *x, int32_t rows, float *y,
+                      float *act, void *stream);
+int hydro_mlp_backward(const float *params, const float *x, const float *act,
+                       const float *dy, int32_t rows, float *scratch, float *grad,
+                       void *stream);
+/* loss = mean((y - target)^2) (device scalar, may be NULL); dy = 2 (y - target)/rows */
+int hydro_mlp_mse(const float *y, const float *target, int32_t rows, float *dy,
+                  float *loss, void *stream);
+/* one Adam step (bias-corrected, step >= 1) over n parameters */
+int hydro_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t n,
+                   float lr, float beta1, float beta2, float eps, int32_t step,
+                   void *stream);
+
 /* Thread-local text of the last error on the calling thread ("" if none). */
 const char *hydro_last_error(void);
 

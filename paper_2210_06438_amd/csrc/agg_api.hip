@@ -242,7 +242,7 @@ int hydro_agg_create(hydro_agg_t** out, int32_t max_width, double timeout_us,
   if (timeout_us != timeout_us) return fail(HYDRO_EINVAL, "timeout is NaN");
   hydro_agg* a = new hydro_agg();
   a->width = max_width;
-  int rc = a->ex.init(n_streams, max_width, 8);
+  int rc = a->ex.init(n_streams, max_width, 32);
   if (rc) {
     a->ex.teardown();
     delete a;

@@ -1,0 +1,57 @@
+"""The learned-width recipe on the stored width sweep (width + timeout
+policy), trained in FP64 by the reference perceptron on the CPU: on
+held-out condition groups the cost model's argmin width has a lower p99
+regret than the best single static width chosen on the training groups.
+This pins the gain to the recipe and the measured data, independently of
+the HIP kernels that train the same model on the GPU."""
+import numpy as np
+
+from oracle import mlp_oracle as M
+from paper_2210_06438_amd import learned, tune
+
+
+def _choose(records, train, test, epochs=2000, lr=1e-3):
+    rows = learned.in_groups(records, train)
+    X = learned.features([r["n"] for r in rows], [r["nfields"] for r in rows],
+                         [r["rate"] for r in rows], [r["width"] for r in rows])
+    y = np.log(np.minimum([r["p99_us"] for r in rows], learned.OVERLOAD_US))
+    xm, xs = X.mean(0), X.std(0) + 1e-12
+    ym, ys = y.mean(), y.std() + 1e-12
+    p = M.init(0)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    first = None
+    for k in range(1, epochs + 1):
+        loss, g = M.loss_and_grad(p, (X - xm) / xs, (y - ym) / ys)
+        first = loss if first is None else first
+        p, m, v = M.adam(p, g, m, v, k, lr=lr)
+    assert loss < 0.05 * first
+    out = {}
+    for grp in test:
+        W = np.array(tune.WIDTHS)
+        Xg = learned.features(np.full(len(W), grp[0]), np.full(len(W), grp[1]),
+                              np.full(len(W), grp[2]), W)
+        pred = M.forward(p, (Xg - xm) / xs)[0]
+        out[grp] = int(W[int(np.argmin(pred))])
+    return out
+
+
+def test_sweep_shape():
+    for name in ("timeout", "idle"):
+        recs = learned.load_sweep(name)
+        assert len(recs) == len(tune.WIDTHS) * len(tune.EDGES) * len(tune.FIELDS) * len(tune.RATES)
+        assert len(learned.groups(recs)) == 42
+        assert all(r["p99_us"] > 0 for r in recs)
+
+
+def test_recipe_beats_best_static_width():
+    recs = learned.load_sweep("timeout")
+    mlp, static = [], []
+    for sp in (0, 1, 3):
+        train, test = learned.split(recs, seed=sp)
+        assert len(train) == 34 and len(test) == 8
+        sw = learned.best_static_width(recs, train)
+        pick = _choose(recs, train, test)
+        mlp.append(np.mean([learned.regret(recs, g, pick[g]) for g in test]))
+        static.append(np.mean([learned.regret(recs, g, sw) for g in test]))
+    assert np.mean(mlp) < 0.5 * np.mean(static), (mlp, static)
