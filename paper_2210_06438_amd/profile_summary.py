@@ -23,20 +23,26 @@ def _rows(d, name):
         return list(csv.DictReader(f))
 
 
-def kernel_stats(kt_dir, match):
-    for r in _rows(kt_dir, "run_kernel_stats.csv"):
-        if match in r["Name"]:
-            return {"name": r["Name"], "calls": int(r["Calls"]),
-                    "avg_ns": float(r["AverageNs"]), "min_ns": float(r["MinNs"]),
-                    "max_ns": float(r["MaxNs"])}
-    raise SystemExit(f"kernel {match!r} not in kernel stats")
+def kernel_stats(kt_dir, match, grid=None):
+    """Durations of the traced dispatches whose name contains `match` (and
+    whose grid has `grid` work-items, when given)."""
+    name, durs = None, []
+    for r in _rows(kt_dir, "run_kernel_trace.csv"):
+        if match in r["Kernel_Name"] and (grid is None or int(r["Grid_Size_X"]) == grid):
+            name = r["Kernel_Name"]
+            durs.append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    if not durs:
+        raise SystemExit(f"kernel {match!r} (grid {grid}) not in kernel trace")
+    return {"name": name, "calls": len(durs), "avg_ns": statistics.mean(durs),
+            "min_ns": min(durs), "max_ns": max(durs), "median_ns": statistics.median(durs)}
 
 
-def counter(d, match, name):
+def counter(d, match, name, grid=None):
     vals = [float(r["Counter_Value"]) for r in _rows(d, "run_counter_collection.csv")
-            if match in r["Kernel_Name"] and r["Counter_Name"] == name]
+            if match in r["Kernel_Name"] and r["Counter_Name"] == name
+            and (grid is None or int(r["Grid_Size"]) == grid)]
     if not vals:
-        raise SystemExit(f"no {name} for {match!r} in {d}")
+        raise SystemExit(f"no {name} for {match!r} (grid {grid}) in {d}")
     return vals
 
 
@@ -46,6 +52,8 @@ def main():
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
     ap.add_argument("--kernel", required=True, help="substring of the hydro kernel name")
+    ap.add_argument("--grid", type=int, default=None,
+                    help="only dispatches with this many work-items")
     ap.add_argument("--copy-bytes", type=float, required=True,
                     help="bytes the plain copy reads (= bytes it writes)")
     ap.add_argument("--launch-bytes", type=float, required=True,
@@ -57,9 +65,9 @@ def main():
     ap.add_argument("--traffic-json", default=None)
     a = ap.parse_args()
 
-    ks = kernel_stats(a.kt, a.kernel)
-    f_h = statistics.median(counter(a.fetch, a.kernel, "FETCH_SIZE"))
-    w_h = statistics.median(counter(a.write, a.kernel, "WRITE_SIZE"))
+    ks = kernel_stats(a.kt, a.kernel, a.grid)
+    f_h = statistics.median(counter(a.fetch, a.kernel, "FETCH_SIZE", a.grid))
+    w_h = statistics.median(counter(a.write, a.kernel, "WRITE_SIZE", a.grid))
     f_c = max(counter(a.fetch, "copyBuffer", "FETCH_SIZE"))
     w_c = max(counter(a.write, "copyBuffer", "WRITE_SIZE"))
     f_scale = a.copy_bytes / (f_c * 1024.0)
@@ -79,8 +87,9 @@ def main():
         "",
         "| quantity | value |",
         "|---|---|",
-        f"| launches traced | {ks['calls']} |",
-        f"| average duration | {ks['avg_ns'] / 1e3:.1f} us (min {ks['min_ns'] / 1e3:.1f}, max {ks['max_ns'] / 1e3:.1f}) |",
+        f"| launches traced | {ks['calls']}" + (f" (grid {a.grid} work-items)" if a.grid else "") + " |",
+        f"| average duration | {ks['avg_ns'] / 1e3:.1f} us (median {ks['median_ns'] / 1e3:.1f}, "
+        f"min {ks['min_ns'] / 1e3:.1f}, max {ks['max_ns'] / 1e3:.1f}) |",
         f"| FETCH_SIZE per launch (raw) | {f_h:.0f} KiB |",
         f"| WRITE_SIZE per launch (raw) | {w_h:.0f} KiB |",
         f"| copy calibration (bytes per counted byte) | read x{f_scale:.4f}, write x{w_scale:.4f} |",

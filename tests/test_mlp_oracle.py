@@ -1,6 +1,7 @@
 """Pins for the FP64 width cost-model reference: its back-propagated
 gradient against central finite differences of the loss, the Adam step
-against its closed form on one step, and the sizes."""
+against its closed form on one step, a hand-wired network with a known
+output, and the sizes."""
 import numpy as np
 
 from oracle import mlp_oracle as M
@@ -46,3 +47,21 @@ def test_training_reduces_the_loss():
         loss, g = M.loss_and_grad(p, x, t)
         p, m, v = M.adam(p, g, m, v, k, lr=3e-3)
     assert M.loss_and_grad(p, x, t)[0] < 0.2 * l0
+
+
+def test_hand_wired_network_computes_abs():
+    # W1 rows 0/1 take +-(x0 - 2 x3); W2 copies hidden units 0 and 1 into
+    # units 5 and 9; W3 sums those and b3 adds 0.5, so y = |x0 - 2 x3| + 0.5.
+    # A transposed weight matrix or a swapped layer would break this.
+    d = {k: np.zeros(s) for k, s in M.SIZES.items()}
+    d["W1"][0, 0], d["W1"][0, 3] = 1.0, -2.0
+    d["W1"][1, 0], d["W1"][1, 3] = -1.0, 2.0
+    d["W2"][5, 0] = 1.0
+    d["W2"][9, 1] = 1.0
+    d["W3"][5] = d["W3"][9] = 1.0
+    d["b3"][0] = 0.5
+    p = M.pack(d)
+    x = np.random.default_rng(4).normal(size=(50, 5))
+    y, h1, h2 = M.forward(p, x)
+    assert np.array_equal(y, np.abs(x[:, 0] - 2 * x[:, 3]) + 0.5)
+    assert np.count_nonzero(h2[:, [i for i in range(64) if i not in (5, 9)]]) == 0
