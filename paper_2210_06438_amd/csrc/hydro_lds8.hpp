@@ -187,6 +187,12 @@ struct Share {
 template <int NF, int MP>
 __device__ __forceinline__ void load_share(const double* __restrict__ src, int t,
                                            Share<NF>& sh) {
+  // An opaque copy of the lane index: the cell indices below are then
+  // recomputed at every call (a few integer ops) instead of being kept live
+  // from the hydro staging to the passive staging, where they would be
+  // spilled and their reloads would wait behind every outstanding load and
+  // store of the wave (the vector memory counter retires in order).
+  asm volatile("" : "+v"(t));
   const gcptr g = as_global(src);
 #pragma unroll
   for (int j = 0; j < Share<NF>::K; ++j) {
@@ -200,6 +206,7 @@ __device__ __forceinline__ void load_share(const double* __restrict__ src, int t
 
 template <int NF>
 __device__ __forceinline__ void store_share(double* lds, int t, const Share<NF>& sh) {
+  asm volatile("" : "+v"(t));   // see load_share
 #pragma unroll
   for (int j = 0; j < Share<NF>::K; ++j) {
     const int e = t + j * Lds8::kThreads;
