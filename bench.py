@@ -166,7 +166,9 @@ def serving_leg(args, torch, hydroagg, np, tensors, dt, dx, dev, model=None):
         n = int(rate * args.serve_seconds)
         task = rng.integers(0, len(edges), n).astype(np.int32)
         arrival = np.cumsum(rng.exponential(1e6 / rate, n))
-        modes = [("aggregated", args.serve_width, True), ("per_task_launch", 1, True)]
+        modes = [("aggregated", args.serve_width, True)]
+        if rate <= args.per_task_max_rate:
+            modes.append(("per_task_launch", 1, True))
         if model is not None:
             mix = {int(N): float(np.mean(edges == N)) for N in (8, 12, 16)}
             modes.append(("timeout_policy_learned_width",
@@ -215,7 +217,10 @@ def main():
     ap.add_argument("--uneven-steps", type=int, default=20)
     ap.add_argument("--uneven-each", type=int, default=1,
                     help="1: also time the uneven batch with one launch per sub-grid")
-    ap.add_argument("--serve-rates", type=float, nargs="*", default=[20000.0, 200000.0])
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=[20000.0, 200000.0, 2000000.0])
+    ap.add_argument("--per-task-max-rate", type=float, default=200000.0,
+                    help="skip the per-task-launch baseline above this rate (it saturates "
+                         "near 60k tasks/s)")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--serve-width", type=int, default=64)
     ap.add_argument("--serve-streams", type=int, default=2)
