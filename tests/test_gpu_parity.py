@@ -174,3 +174,14 @@ def test_full_size_batch_sampled(dev, oracle_mod):
     assert np.all(normwise(interior(got, 8), interior(ref, 8)) <= TOL)
     a = amax.cpu().numpy()[sample]
     assert np.max(np.abs(a - ref_amax) / ref_amax) <= ATOL_AMAX
+
+
+def test_x_only_data_has_no_transverse_update_on_gpu(dev, oracle_mod):
+    from tests.test_oracle_pins import x_only_block
+    for n, nf in ((8, 11), (12, 6), (16, 11)):
+        U = np.stack([x_only_block(n, nf, seed=n + nf + s) for s in range(3)])
+        got, amax = run_gpu(U, 0.002, 0.05)
+        I = interior(got, n)
+        assert np.array_equal(I, np.broadcast_to(I[:, :, :1, :1, :], I.shape))
+        assert not I[:, 2].any() and not I[:, 3].any()
+        check(U, 0.002, 0.05, oracle_mod)

@@ -14,6 +14,9 @@ mathematics or the paper fixes, not against a retyped copy of its formulas.
   contact              -> p and v stay uniform
   uniform composition  -> mass fractions stay uniform
   power-of-two scaling -> bitwise equivariance
+  data varying along x -> transverse flux differences vanish exactly: every
+                          (y, z) row of the output is the same, bitwise, and
+                          zero transverse momentum stays exactly zero
 """
 import math
 
@@ -408,3 +411,31 @@ def test_oracle_rejects_bad_arguments(oracle_mod):
         oracle_mod.step(U, dt=0.1, dx=0.0)
     with pytest.raises(ValueError):
         oracle_mod.step(U[:, :, :10], dt=0.1, dx=0.1)
+
+
+# ------------------------------------------------- one-dimensional data
+def x_only_block(n, nf, seed):
+    """A block whose primitives vary only along x (v_y = v_z = 0)."""
+    M = n + 6
+    rng = np.random.default_rng(seed)
+    W = np.empty((nf, M))
+    W[0] = 1.0 + 0.3 * rng.uniform(-1, 1, M)
+    W[1] = 0.4 * rng.uniform(-1, 1, M)
+    W[2] = W[3] = 0.0
+    W[4] = 1.0 + 0.3 * rng.uniform(-1, 1, M)
+    for f in range(5, nf):
+        W[f] = W[0] * rng.uniform(0.05, 0.3, M)
+    Wf = np.broadcast_to(W[:, None, None, :], (nf, M, M, M)).copy()
+    return block_from_primitive(Wf)
+
+
+@pytest.mark.parametrize("n,nf", [(8, 11), (12, 6), (16, 11)])
+def test_x_only_data_has_no_transverse_update(oracle_mod, n, nf):
+    U = x_only_block(n, nf, seed=n + nf)[None]
+    out, amax = oracle_mod.step(U, 0.002, 0.05)
+    I = interior(out, n)[0]
+    # identical rows along y and z
+    assert np.array_equal(I, np.broadcast_to(I[:, :1, :1, :], I.shape))
+    # transverse momenta exactly zero, and the x update is not trivial
+    assert not I[2].any() and not I[3].any()
+    assert not np.array_equal(I, interior(U, n)[0])
