@@ -157,8 +157,12 @@ def serving_leg(args, torch, hydroagg, np, tensors, dt, dx, dev, model=None):
         k = max(int(budget * share[N] / tot // size[N]), 1 if share[N] else 0)
         arenas.append((torch.zeros(max(k, 1) * size[N] // 8, dtype=torch.float64, device=dev), k))
     used = sum(k * size[N] for (t, k), N in zip(arenas, (8, 12, 16)))
+    # the same bytes cut into interior-only slabs: (n/(n+6))^3 of the size each
+    isize = {N: nfields * N ** 3 * 8 for N in (8, 12, 16)}
+    iarenas = [(t, int(k * size[N] // isize[N])) for (t, k), N in zip(arenas, (8, 12, 16))]
     out = {"pool": int(len(edges)), "hbm_budget_bytes": int(used),
            "slabs": {N: k for (t, k), N in zip(arenas, (8, 12, 16))},
+           "interior_slabs": {N: k for (t, k), N in zip(iarenas, (8, 12, 16))},
            "width": args.serve_width, "timeout_us": 50.0, "streams": args.serve_streams,
            "runs": []}
     rng = np.random.Generator(np.random.PCG64(4))
@@ -169,15 +173,20 @@ def serving_leg(args, torch, hydroagg, np, tensors, dt, dx, dev, model=None):
         modes = [("aggregated", args.serve_width, True)]
         if rate <= args.per_task_max_rate:
             modes.append(("per_task_launch", 1, True))
+        if rate >= 200000.0:
+            modes.append(("aggregated_interior_slabs", args.serve_width, True))
         if model is not None:
             mix = {int(N): float(np.mean(edges == N)) for N in (8, 12, 16)}
             modes.append(("timeout_policy_learned_width",
                           model.choose_mix(mix, nfields, rate), False))
         for label, width, idle in modes:
+            inner = label == "aggregated_interior_slabs"
             lat, am, _, st = hydroagg.serve_run(
-                pool, task, arrival, nfields=nfields, dt=dt, dx=dx, slab_arenas=arenas,
+                pool, task, arrival, nfields=nfields, dt=dt, dx=dx,
+                slab_arenas=iarenas if inner else arenas,
                 max_width=width, timeout_us=50.0, n_streams=args.serve_streams,
-                flush_when_idle=idle)
+                flush_when_idle=idle,
+                out_layout=hydroagg.OUT_INTERIOR if inner else hydroagg.OUT_STORED)
             span = st["makespan_us"] * 1e-6
             rec = {"mode": label, "rate_per_s": rate, "tasks": n, "width": width,
                    "flush_when_idle": idle,
@@ -226,6 +235,8 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--serve-budget-mb", type=float, default=64.0)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-width leg")
+    ap.add_argument("--interior-leg", type=int, default=1,
+                    help="1: also time the headline step with interior-only outputs")
     ap.add_argument("--learned-splits", type=int, default=10)
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads (0 = OMP_NUM_THREADS or all cores)")
@@ -279,6 +290,24 @@ def main():
     cells = count * n ** 3
     value = cells / (ms * 1e-3)
     log(f"aggregated: {ms * 1e3:.1f} us/step, {value / 1e9:.3f} G cell-updates/s")
+
+    # ---- the same step writing interior-only outputs (reported beside) -----
+    interior_ms = None
+    if args.interior_leg:
+        u_int = torch.empty((count, nf, n, n, n), dtype=torch.float64, device=dev)
+        plan_i = hydroagg.Plan(hydroagg.subgrids(u_in, u_int))
+        for _ in range(args.warmup):
+            plan_i.graph(dt, dx, amax, stream)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            plan_i.graph(dt, dx, amax, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        interior_ms = e0.elapsed_time(e1) / args.steps
+        plan_i.close()
+        del u_int
+        log(f"interior-only outputs: {interior_ms * 1e3:.1f} us/step")
 
     # ---- baseline: the same kernel, one launch per sub-grid ----------------
     each_ms = None
@@ -385,6 +414,9 @@ def main():
             "value": round(cells / (each_ms * 1e-3), 1), "ms_per_step": round(each_ms, 4),
             "launches_per_step": count},
         "aggregation_speedup": None if each_ms is None else round(each_ms / ms, 2),
+        "interior_output_layout": None if interior_ms is None else {
+            "ms_per_step": round(interior_ms, 5), "value": round(cells / (interior_ms * 1e-3), 1),
+            "note": "same step and inputs, u_out in the interior-only layout (not the headline)"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "uneven": uneven,

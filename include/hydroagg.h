@@ -11,9 +11,13 @@
  * of one launch per sub-grid (the paper's strategy 3, Section V-D).  gamma is
  * fixed at 5/3.
  *
- * Memory layout of one sub-grid (both u_in and u_out): float64, structure of
- * arrays [nfields][M][M][M], M = n + 6, x fastest, linear index
+ * Memory layout of one sub-grid (u_in, and u_out by default): float64,
+ * structure of arrays [nfields][M][M][M], M = n + 6, x fastest, linear index
  * ((f*M + z)*M + y)*M + x.  Interior cells are x, y, z in [3, n+3).
+ * With out_layout = HYDRO_OUT_INTERIOR, u_out holds the interior only:
+ * [nfields][n][n][n], linear index ((f*n + z)*n + y)*n + x for interior cell
+ * (x+3, y+3, z+3) of the stored layout -- every element is written, rows are
+ * whole 64-byte multiples, and the buffer is (n/(n+6))^3 of the stored size.
  * Fields: 0 rho, 1 sx, 2 sy, 3 sz, 4 egas (total energy density), 5 tau
  * (passive entropy tracer), 6..10 partial densities of 5 species (nfields 11).
  *
@@ -47,15 +51,20 @@ extern "C" {
 
 #define HYDRO_GHOST 3
 
+/* Layouts of u_out (hydro_subgrid_t.out_layout). */
+#define HYDRO_OUT_STORED 0    /* the (n+6)^3 layout of u_in; interior written */
+#define HYDRO_OUT_INTERIOR 1  /* interior only, [nfields][n][n][n]            */
+
 /* One sub-grid task: 32 bytes. */
 typedef struct {
   const double *u_in; /* device; [nfields][M][M][M]; read-only                 */
-  double *u_out;      /* device; same shape; only the interior n^3 is written;
-                         must not alias u_in                                  */
+  double *u_out;      /* device; layout per out_layout: the shape of u_in with
+                         only the interior n^3 written (STORED), or the
+                         interior alone (INTERIOR); must not overlap u_in     */
   int32_t n;          /* interior edge: 8, 12 or 16                            */
   int32_t nfields;    /* 6 or 11                                               */
   int32_t level;      /* octree level: cell width dx_s = dx * 2^-level, 0..30  */
-  int32_t reserved;   /* must be 0                                             */
+  int32_t out_layout; /* HYDRO_OUT_STORED (0) or HYDRO_OUT_INTERIOR (1)       */
 } hydro_subgrid_t;
 
 /*
@@ -70,10 +79,12 @@ typedef struct {
  *            signal speed (the quantity behind the Courant limit, Sec. IV-B).
  *   stream   hipStream_t to enqueue on (NULL = default stream).
  * Per sub-grid: U_out = U - dt/dx_s * sum_d (F_{d,i+1/2} - F_{d,i-1/2}) on
- * the interior; ghost cells of u_out are never written.
+ * the interior; in the stored layout the ghost cells of u_out are never
+ * written.  Both layouts give bitwise the same values.
  * Errors: HYDRO_EINVAL for sg == NULL with count > 0, count < 0, n not in
- * {8,12,16}, nfields not in {6,11}, level outside 0..30, reserved != 0, NULL
- * or aliased u_in/u_out, dt < 0 or not finite, dx <= 0 or not finite;
+ * {8,12,16}, nfields not in {6,11}, level outside 0..30, out_layout not 0 or
+ * 1, NULL u_in/u_out, u_out overlapping u_in (per sub-grid), dt < 0 or not
+ * finite, dx <= 0 or not finite;
  * HYDRO_EHIP if a launch or copy fails.  count = 0 is a no-op success.
  */
 int hydro_step(const hydro_subgrid_t *sg, int32_t count, double dt, double dx,
@@ -159,8 +170,9 @@ int hydro_agg_destroy(hydro_agg_t *agg);
  * task_subgrid[i] and arrives at arrival_us[i] (microseconds after the loop
  * starts, non-decreasing; the caller draws them, e.g. Poisson).  An arrived
  * task is admitted as soon as an output slab of its edge class is free
- * (slabs[e] slabs of (n+6)^3 x nfields doubles at slab_base[e] for
- * n = 8, 12, 16 -- the HBM budget of the loop), is submitted to an
+ * (slabs[e] slabs at slab_base[e] for n = 8, 12, 16 -- the HBM budget of the
+ * loop; a slab is nfields x (n+6)^3 doubles with out_layout STORED, nfields x
+ * n^3 with INTERIOR, so the same budget holds more tasks), is submitted to an
  * aggregator configured by cfg, and releases its slab when its batch has
  * completed (unless keep_slabs).  Per task the loop reports latency_us =
  * completion observed - arrival, and optionally amax and the slab used.
@@ -176,6 +188,7 @@ typedef struct {
   double *slab_base[3];
   int32_t slabs[3];
   int32_t keep_slabs;
+  int32_t out_layout;   /* layout of the output slabs: HYDRO_OUT_STORED/INTERIOR */
 } hydro_serve_config_t;
 
 typedef struct {

@@ -54,6 +54,8 @@ class HipExec {
       created_ = s + 1;
     }
     slots_.resize((size_t)ns_ * slots_per_stream);
+    HIP_OK(hipHostMalloc((void**)&flags_, sizeof(uint64_t) * slots_.size(), hipHostMallocDefault));
+    for (size_t k = 0; k < slots_.size(); ++k) flags_[k] = 0;
     for (Slot& sl : slots_) {
       HIP_OK(hipHostMalloc((void**)&sl.htab, sizeof(DevDesc) * cap_, hipHostMallocDefault));
       HIP_OK(hipMalloc((void**)&sl.dtab, sizeof(DevDesc) * cap_));
@@ -74,6 +76,8 @@ class HipExec {
       if (sl.damax) (void)hipFree(sl.damax);
     }
     slots_.clear();
+    if (flags_) (void)hipHostFree(flags_);
+    flags_ = nullptr;
     for (int s = 0; s < created_; ++s) (void)hipStreamDestroy(streams_[s]);
     created_ = 0;
   }
@@ -81,15 +85,13 @@ class HipExec {
   int streams() const { return ns_; }
   hipStream_t stream(int s) const { return streams_[s]; }
 
+  // A stream runs its batches in order, so it is idle once its newest batch
+  // has finished (or was already collected).
   bool idle(int s) {
-    for (auto& kv : live_) {
-      Slot& sl = slots_[kv.second];
-      if (sl.stream == s && !sl.finished) {
-        if (hipEventQuery(sl.ev) != hipSuccess) return false;
-        sl.finished = true;
-      }
-    }
-    return true;
+    const uint64_t b = last_[s];
+    if (b == 0 || retired_.count(b)) return true;
+    auto it = live_.find(b);
+    return it == live_.end() || finished(it->second);
   }
 
   int launch(int s, const Task* t, int n, double dt, double dx, uint64_t batch) {
@@ -113,7 +115,8 @@ class HipExec {
       DevDesc& d = sl.htab[fill[hydro::api::class_of_task(t[i].n, t[i].nfields)]++];
       d.u_in = t[i].u_in;
       d.u_out = t[i].u_out;
-      d.level = t[i].level;
+      d.level = (int16_t)t[i].level;
+      d.compact = (int16_t)(t[i].out_layout == HYDRO_OUT_INTERIOR);
       d.index = i;
     }
     hipStream_t st = streams_[s];
@@ -124,6 +127,10 @@ class HipExec {
       if (rc) return rc;
     }
     HIP_OK(hipMemcpyAsync(sl.hamax, sl.damax, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    // Completion word: the stream stores the batch id into pinned host memory
+    // after the amax copy, so polling completion is a memory read, not a
+    // runtime call.  The event serves blocking waits.
+    HIP_OK(hipStreamWriteValue64(st, &flags_[k], batch, 0));
     HIP_OK(hipEventRecord(sl.ev, st));
     sl.busy = true;
     sl.finished = false;
@@ -132,16 +139,14 @@ class HipExec {
     sl.batch = batch;
     live_[batch] = k;
     order_.push_back(batch);
+    last_[s] = batch;
     return HYDRO_OK;
   }
 
   bool done(uint64_t batch) {
     auto r = retired_.find(batch);
     if (r != retired_.end()) return true;
-    Slot& sl = slots_[live_.at(batch)];
-    if (sl.finished) return true;
-    if (hipEventQuery(sl.ev) == hipSuccess) sl.finished = true;
-    return sl.finished;
+    return finished(live_.at(batch));
   }
 
   int wait(uint64_t batch) {
@@ -187,6 +192,13 @@ class HipExec {
     uint64_t batch = 0;
   };
 
+  bool finished(int k) {
+    Slot& sl = slots_[k];
+    if (!sl.finished && __atomic_load_n(&flags_[k], __ATOMIC_ACQUIRE) == sl.batch)
+      sl.finished = true;
+    return sl.finished;
+  }
+
   int free_slot() const {
     for (size_t k = 0; k < slots_.size(); ++k)
       if (!slots_[k].busy) return (int)k;
@@ -208,6 +220,8 @@ class HipExec {
   int ns_ = 0, created_ = 0, cap_ = 0;
   hipStream_t streams_[8] = {};
   std::vector<Slot> slots_;
+  uint64_t* flags_ = nullptr;   // pinned; flags_[k] = id of the last finished batch of slot k
+  uint64_t last_[8] = {};       // newest batch launched on each stream
   std::unordered_map<uint64_t, int> live_;
   std::deque<uint64_t> order_;
   std::unordered_map<uint64_t, std::vector<double>> retired_;
@@ -215,10 +229,13 @@ class HipExec {
 
 using Policy = hydro::AggPolicy<HipExec, SteadyClock>;
 
-uint64_t task_bytes(const hydro_subgrid_t& s) {
-  const uint64_t M = (uint64_t)s.n + 2 * HYDRO_GHOST;
-  return (uint64_t)s.nfields * M * M * M * sizeof(double);
+// Output bytes of a task (what the byte budget of the aggregator counts).
+uint64_t out_bytes(int n, int nfields, int out_layout) {
+  const uint64_t e = out_layout == HYDRO_OUT_INTERIOR ? (uint64_t)n : (uint64_t)n + 2 * HYDRO_GHOST;
+  return (uint64_t)nfields * e * e * e * sizeof(double);
 }
+
+uint64_t task_bytes(const hydro_subgrid_t& s) { return out_bytes(s.n, s.nfields, s.out_layout); }
 
 }  // namespace
 
@@ -265,6 +282,7 @@ int hydro_submit(hydro_agg_t* a, const hydro_subgrid_t* sg, double dt, double dx
   t.n = sg->n;
   t.nfields = sg->nfields;
   t.level = sg->level;
+  t.out_layout = sg->out_layout;
   t.bytes = task_bytes(*sg);
   std::lock_guard<std::mutex> lk(a->mu);
   rc = a->pol->submit(t, dt, dx, ticket);
@@ -353,6 +371,7 @@ namespace {
 // memory (the HBM budget of the loop).
 struct SlabPool {
   std::vector<double*> free_list;
+  uint64_t words = 0;  // doubles per slab
 };
 
 }  // namespace
@@ -367,6 +386,8 @@ extern "C" int hydro_serve_run(const hydro_serve_config_t* cfg, const hydro_subg
       !latency_us || !stats)
     return fail(HYDRO_EINVAL, "NULL or empty argument");
   if (cfg->max_width < 1 || cfg->n_streams < 1) return fail(HYDRO_EINVAL, "bad aggregator config");
+  if (cfg->out_layout != HYDRO_OUT_STORED && cfg->out_layout != HYDRO_OUT_INTERIOR)
+    return fail(HYDRO_EINVAL, "out_layout %d", cfg->out_layout);
   int rc = HYDRO_OK;
   for (int i = 1; i < ntasks; ++i)
     if (!(arrival_us[i] >= arrival_us[i - 1]))
@@ -377,8 +398,8 @@ extern "C" int hydro_serve_run(const hydro_serve_config_t* cfg, const hydro_subg
     const int n = 8 + 4 * e;
     if (cfg->slabs[e] < 0) return fail(HYDRO_EINVAL, "negative slab count");
     if (cfg->slabs[e] > 0 && !cfg->slab_base[e]) return fail(HYDRO_EINVAL, "NULL slab arena");
-    const uint64_t M = (uint64_t)n + 2 * HYDRO_GHOST;
-    const uint64_t words = (uint64_t)cfg->nfields * M * M * M;
+    const uint64_t words = out_bytes(n, cfg->nfields, cfg->out_layout) / sizeof(double);
+    pools[e].words = words;
     for (int k = cfg->slabs[e] - 1; k >= 0; --k)
       pools[e].free_list.push_back(cfg->slab_base[e] + (uint64_t)k * words);
   }
@@ -390,8 +411,19 @@ extern "C" int hydro_serve_run(const hydro_serve_config_t* cfg, const hydro_subg
     if (cfg->slabs[e] == 0) return fail(HYDRO_EINVAL, "sub-grid %d: no slabs for n=%d", s, pool[s].n);
     hydro_subgrid_t probe = pool[s];
     probe.u_out = cfg->slab_base[e];
+    probe.out_layout = cfg->out_layout;
     rc = hydro::api::validate_batch(&probe, 1, cfg->dt, cfg->dx);
     if (rc) return rc;
+    // no slab of any class may overlap a resident input
+    const uint64_t in_bytes = out_bytes(pool[s].n, pool[s].nfields, HYDRO_OUT_STORED);
+    const uintptr_t a0 = (uintptr_t)pool[s].u_in, a1 = a0 + in_bytes;
+    for (int f = 0; f < 3; ++f) {
+      if (cfg->slabs[f] == 0) continue;
+      const uintptr_t b0 = (uintptr_t)cfg->slab_base[f];
+      const uintptr_t b1 = b0 + (uint64_t)cfg->slabs[f] * pools[f].words * sizeof(double);
+      if (a0 < b1 && b0 < a1)
+        return fail(HYDRO_EINVAL, "sub-grid %d: the slab arena of class %d overlaps it", s, f);
+    }
   }
   for (int i = 0; i < ntasks; ++i)
     if (task_subgrid[i] < 0 || task_subgrid[i] >= pool_count)
@@ -438,7 +470,8 @@ extern "C" int hydro_serve_run(const hydro_serve_config_t* cfg, const hydro_subg
         t.n = src.n;
         t.nfields = src.nfields;
         t.level = src.level;
-        t.bytes = task_bytes(src);
+        t.out_layout = cfg->out_layout;
+        t.bytes = out_bytes(src.n, src.nfields, cfg->out_layout);
         uint64_t ticket = 0;
         rc = agg->pol->submit(t, cfg->dt, cfg->dx, &ticket);
         if (rc) break;

@@ -46,6 +46,7 @@ struct Task {
   uint64_t ticket;
   uint64_t bytes;
   double t_submit;
+  int32_t out_layout = 0;  // HYDRO_OUT_STORED or HYDRO_OUT_INTERIOR
 };
 
 struct AggStats {
@@ -227,9 +228,14 @@ class AggPolicy {
   }
 
   void collect() {
-    // batches on one stream finish in order; across streams in any order
+    // Batches on one stream finish in order, across streams in any order:
+    // once a batch is found unfinished, later batches of its stream are not
+    // polled.
+    uint32_t blocked = 0;
     for (auto it = inflight_.begin(); it != inflight_.end();) {
-      if (!ex_.done(it->batch)) {
+      const uint32_t bit = 1u << (it->stream & 31);
+      if ((blocked & bit) || !ex_.done(it->batch)) {
+        blocked |= bit;
         ++it;
         continue;
       }

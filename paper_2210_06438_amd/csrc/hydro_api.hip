@@ -116,12 +116,18 @@ int validate(const hydro_subgrid_t* sg, int32_t count, double dt, double dx) {
     if (class_of(s.n, s.nfields) < 0)
       return fail(HYDRO_EINVAL, "sub-grid %d: unsupported n=%d nfields=%d", i, s.n, s.nfields);
     if (!s.u_in || !s.u_out) return fail(HYDRO_EINVAL, "sub-grid %d: NULL buffer", i);
-    if ((const void*)s.u_in == (const void*)s.u_out)
-      return fail(HYDRO_EINVAL, "sub-grid %d: u_out aliases u_in", i);
+    if (s.out_layout != HYDRO_OUT_STORED && s.out_layout != HYDRO_OUT_INTERIOR)
+      return fail(HYDRO_EINVAL, "sub-grid %d: out_layout %d", i, s.out_layout);
+    {
+      const uint64_t M = (uint64_t)s.n + 2 * HYDRO_GHOST;
+      const uint64_t e = s.out_layout == HYDRO_OUT_INTERIOR ? (uint64_t)s.n : M;
+      const uintptr_t a0 = (uintptr_t)s.u_in, a1 = a0 + s.nfields * M * M * M * sizeof(double);
+      const uintptr_t b0 = (uintptr_t)s.u_out, b1 = b0 + s.nfields * e * e * e * sizeof(double);
+      if (a0 < b1 && b0 < a1) return fail(HYDRO_EINVAL, "sub-grid %d: u_out overlaps u_in", i);
+    }
     if (((uintptr_t)s.u_in | (uintptr_t)s.u_out) & 15)
       return fail(HYDRO_EINVAL, "sub-grid %d: buffers must be 16-byte aligned", i);
     if (s.level < 0 || s.level > 30) return fail(HYDRO_EINVAL, "sub-grid %d: level %d", i, s.level);
-    if (s.reserved != 0) return fail(HYDRO_EINVAL, "sub-grid %d: reserved must be 0", i);
   }
   return HYDRO_OK;
 }
@@ -195,7 +201,8 @@ DevDesc to_dev(const hydro_subgrid_t& s, int index) {
   DevDesc d;
   d.u_in = s.u_in;
   d.u_out = s.u_out;
-  d.level = s.level;
+  d.level = (int16_t)s.level;
+  d.compact = (int16_t)(s.out_layout == HYDRO_OUT_INTERIOR);
   d.index = index;
   return d;
 }

@@ -52,8 +52,9 @@ __device__ __forceinline__ double sqrt_pos(double y) {
 struct DevDesc {
   const double* u_in;
   double* u_out;
-  int32_t level;
-  int32_t index;  // position in the caller's batch (amax slot)
+  int16_t level;
+  int16_t compact;  // 1: u_out holds the interior only, [F][n][n][n]
+  int32_t index;    // position in the caller's batch (amax slot)
 };
 
 // Descriptors carried by value in the kernel arguments (small batches and

@@ -256,8 +256,8 @@ __device__ __forceinline__ void recon_at(Recon<K>& rc, const double (&q)[K],
 // slot (combined with an atomic max of the bit pattern, which orders like the
 // values for non-negative doubles; the slot is zeroed before the launch).
 template <int F, int MP, bool MULTI>
-__device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int lox, int loy,
-                                          int loz, double dt, double dx,
+__device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int oy, int oz,
+                                          int lox, int loy, int loz, double dt, double dx,
                                           double* __restrict__ amax_out) {
   constexpr int M = Lds8::M;
   constexpr int N = Lds8::N;
@@ -287,9 +287,18 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int lox, in
   const int gstride = Frame<MP>::stride(dir);
   const double lambda = dt / ldexp(dx, -d.level);
   const double* __restrict__ uin = d.u_in + org;
-  double* __restrict__ uout = d.u_out + org;
-  // z lanes write column (a, b) from c = loz on, if they own (a, b)
+  // z lanes write column (a, b) from c = loz on, if they own (a, b).  Output
+  // element (field k, block-local z = c) of the column is
+  // uout[k * ofs + obase + c * ostride], in the stored layout of u_in or in
+  // the interior-only layout [F][n][n][n] (block origin (ox, oy, oz)).
   const bool owner = a >= lox && b >= loy;
+  constexpr int NI = MP - 2 * kGhost;
+  const bool compact = d.compact != 0;
+  double* __restrict__ uout = compact ? d.u_out : d.u_out + org;
+  const long ofs = compact ? (long)NI * NI * NI : FS;
+  const int ostride = compact ? NI * NI : MP * MP;
+  const int obase = compact ? (oz * NI + oy + b) * NI + ox + a
+                            : Frame<MP>::line(2, a, b, kGhost);
 
   // ---- stage the hydro core ---------------------------------------------
   {
@@ -361,7 +370,7 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int lox, in
         const int cell = k * P + lbase + c * lstride;
         if (owner && c >= loz)
           __builtin_nontemporal_store(held[cell] - lambda * acc[cell],
-                                      &as_global(uout)[k * FS + gbase + (c + kGhost) * gstride]);
+                                      &as_global(uout)[k * ofs + obase + c * ostride]);
         acc[cell] = 0.0;
       }
     }
@@ -412,7 +421,7 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int lox, in
         const int cell = (p % 2) * P + lbase + c * lstride;
         if (owner && c >= loz)
           __builtin_nontemporal_store(L[c] - lambda * acc[cell],
-                                      &as_global(uout)[(5 + p) * FS + gbase + (c + kGhost) * gstride]);
+                                      &as_global(uout)[(5 + p) * ofs + obase + c * ostride]);
         acc[cell] = 0.0;
       }
     }
@@ -441,9 +450,14 @@ struct Blocks {
   static constexpr int kPerSubgrid = NB * NB * NB;
   static constexpr int kShift = N - 8;             // origin of the second block
   static_assert(N == 8 || N == 12 || N == 16, "edges 8, 12, 16");
-  __device__ static __forceinline__ void geo(int b, int& org, int& lox, int& loy, int& loz) {
+  // b -> stored offset of the block frame (org), block origin in interior
+  // coordinates (ox, oy, oz), first owned block-local coordinates (lo*).
+  __device__ static __forceinline__ void geo(int b, int& org, int& ox, int& oy, int& oz,
+                                             int& lox, int& loy, int& loz) {
     const int bx = b % NB, by = (b / NB) % NB, bz = b / (NB * NB);
-    const int ox = bx * kShift, oy = by * kShift, oz = bz * kShift;
+    ox = bx * kShift;
+    oy = by * kShift;
+    oz = bz * kShift;
     org = (oz * MP + oy) * MP + ox;
     lox = bx ? 16 - N : 0;   // the second block owns the parent cells 8..N-1
     loy = by ? 16 - N : 0;
@@ -463,10 +477,10 @@ __global__ void __launch_bounds__(Lds8::kThreads, 2)
   const int s = B == 1 ? w : (w / (8 * B)) * 8 + (w & 7);
   const int b = B == 1 ? 0 : (w >> 3) % B;
   if (s >= count) return;
-  int org, lox, loy, loz;
-  Blocks<MP>::geo(b, org, lox, loy, loz);
+  int org, ox, oy, oz, lox, loy, loz;
+  Blocks<MP>::geo(b, org, ox, oy, oz, lox, loy, loz);
   const DevDesc d = table[s];
-  lds8_step<F, MP, (B > 1)>(d, org, lox, loy, loz, dt, dx, amax_out);
+  lds8_step<F, MP, (B > 1)>(d, org, ox, oy, oz, lox, loy, loz, dt, dx, amax_out);
 }
 
 // Small batches: descriptors in the kernel arguments.
@@ -475,10 +489,10 @@ __global__ void __launch_bounds__(Lds8::kThreads, 2)
     hydro_lds8_arg_kernel(ArgDescs descs, double dt, double dx,
                           double* __restrict__ amax_out) {
   constexpr int B = Blocks<MP>::kPerSubgrid;
-  int org, lox, loy, loz;
-  Blocks<MP>::geo(blockIdx.x % B, org, lox, loy, loz);
+  int org, ox, oy, oz, lox, loy, loz;
+  Blocks<MP>::geo(blockIdx.x % B, org, ox, oy, oz, lox, loy, loz);
   const DevDesc d = descs.d[blockIdx.x / B];
-  lds8_step<F, MP, (B > 1)>(d, org, lox, loy, loz, dt, dx, amax_out);
+  lds8_step<F, MP, (B > 1)>(d, org, ox, oy, oz, lox, loy, loz, dt, dx, amax_out);
 }
 
 // amax slots of a batch set to zero before a multi-block launch (a kernel,

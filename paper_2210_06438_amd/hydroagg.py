@@ -15,6 +15,8 @@ LIB_PATH = os.path.join(HERE, "libhydroagg.so")
 
 HYDRO_OK, HYDRO_EINVAL, HYDRO_EHIP, HYDRO_ENOMEM, HYDRO_EAGAIN = 0, -1, -2, -3, -4
 GHOST = 3
+OUT_STORED = 0      # u_out in the (n+6)^3 layout of u_in, interior written
+OUT_INTERIOR = 1    # u_out holds the interior only, [F][n][n][n]
 
 
 class HydroError(RuntimeError):
@@ -30,7 +32,7 @@ class hydro_subgrid_t(ctypes.Structure):
         ("n", ctypes.c_int32),
         ("nfields", ctypes.c_int32),
         ("level", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("out_layout", ctypes.c_int32),
     ]
 
 
@@ -54,7 +56,7 @@ class hydro_serve_config_t(ctypes.Structure):
                 ("n_streams", ctypes.c_int32), ("flush_when_idle", ctypes.c_int32),
                 ("nfields", ctypes.c_int32), ("dt", ctypes.c_double), ("dx", ctypes.c_double),
                 ("slab_base", ctypes.c_void_p * 3), ("slabs", ctypes.c_int32 * 3),
-                ("keep_slabs", ctypes.c_int32)]
+                ("keep_slabs", ctypes.c_int32), ("out_layout", ctypes.c_int32)]
 
 
 class hydro_serve_stats_t(ctypes.Structure):
@@ -138,26 +140,32 @@ def _stream(stream) -> int:
 
 
 def subgrids(u_in, u_out, levels=None, n=None, nfields=None):
-    """Descriptor array for a batch stored as float64 tensors
-    [count, F, M, M, M] on the GPU (or for explicit lists of pointers)."""
+    """Descriptor array for a batch stored as float64 tensors: u_in
+    [count, F, M, M, M] on the GPU; u_out either of the same shape (the
+    stored layout) or [count, F, n, n, n] (the interior-only layout)."""
     count = int(u_in.shape[0])
     F = int(u_in.shape[1]) if nfields is None else nfields
     M = int(u_in.shape[2])
     n = M - 2 * GHOST if n is None else n
-    if tuple(u_out.shape) != tuple(u_in.shape):
-        raise ValueError("u_out must have the shape of u_in")
+    if tuple(u_out.shape) == tuple(u_in.shape):
+        layout, e = OUT_STORED, M
+    elif tuple(u_out.shape) == (count, F, n, n, n):
+        layout, e = OUT_INTERIOR, n
+    else:
+        raise ValueError("u_out must have the shape of u_in or [count, F, n, n, n]")
     if not (u_in.is_contiguous() and u_out.is_contiguous()):
         raise ValueError("tensors must be contiguous")
-    stride = F * M * M * M * 8
+    stride_in = F * M * M * M * 8
+    stride_out = F * e * e * e * 8
     arr = (hydro_subgrid_t * max(count, 1))()
     b_in, b_out = _ptr(u_in), _ptr(u_out)
     for s in range(count):
-        arr[s].u_in = b_in + s * stride
-        arr[s].u_out = b_out + s * stride
+        arr[s].u_in = b_in + s * stride_in
+        arr[s].u_out = b_out + s * stride_out
         arr[s].n = n
         arr[s].nfields = F
         arr[s].level = 0 if levels is None else int(levels[s])
-        arr[s].reserved = 0
+        arr[s].out_layout = layout
     return arr, count
 
 
@@ -286,10 +294,10 @@ class Aggregator:
 
 def serve_run(pool_descs, task_subgrid, arrival_us, *, nfields, dt, dx, slab_arenas,
               max_width=64, timeout_us=50.0, n_streams=2, flush_when_idle=True,
-              keep_slabs=False, want_slabs=False):
+              keep_slabs=False, want_slabs=False, out_layout=OUT_STORED):
     """Run the serving loop (hydro_serve_run).  slab_arenas: three (tensor or
-    None, nslabs) pairs for n = 8, 12, 16.  Returns (latency_us, amax, slabs,
-    stats) as numpy arrays / dict."""
+    None, nslabs) pairs for n = 8, 12, 16, slabs in `out_layout`.  Returns
+    (latency_us, amax, slabs, stats) as numpy arrays / dict."""
     import numpy as np
     arr, count = pool_descs
     task_subgrid = np.ascontiguousarray(task_subgrid, dtype=np.int32)
@@ -299,6 +307,7 @@ def serve_run(pool_descs, task_subgrid, arrival_us, *, nfields, dt, dx, slab_are
     cfg.max_width, cfg.timeout_us, cfg.n_streams = int(max_width), float(timeout_us), int(n_streams)
     cfg.flush_when_idle, cfg.nfields = int(bool(flush_when_idle)), int(nfields)
     cfg.dt, cfg.dx, cfg.keep_slabs = float(dt), float(dx), int(bool(keep_slabs))
+    cfg.out_layout = int(out_layout)
     for e, (t, k) in enumerate(slab_arenas):
         cfg.slab_base[e] = _ptr(t) if t is not None else 0
         cfg.slabs[e] = int(k)

@@ -55,8 +55,12 @@ struct FakeExec {
     return 0;
   }
   bool done(uint64_t id) { return b.at(id).done; }
+  // A stream runs its batches in order: waiting for one also completes every
+  // earlier batch of its stream.
   int wait(uint64_t id) {
-    b.at(id).done = true;
+    const int s = b.at(id).stream;
+    for (auto& kv : b)
+      if (kv.first <= id && kv.second.stream == s) kv.second.done = true;
     return 0;
   }
   void results(uint64_t id, double* amax) {
@@ -187,9 +191,11 @@ static void streams_and_wait() {
   CHECK(p.wait(c, &am) == 0 && am == 2.5);      // wait flushes and completes
   CHECK(p.wait(c, &am) == -1);
   int done = 0;
-  CHECK(p.poll(a, &done, &am) == 0 && done == 0);
-  CHECK(p.drain() == 0);
+  // c was queued behind a on stream 0, so a is done too; b (stream 1) is not
   CHECK(p.poll(a, &done, &am) == 0 && done == 1 && am == 0.5);
+  CHECK(p.poll(b, &done, &am) == 0 && done == 0);
+  CHECK(p.drain() == 0);
+  CHECK(p.poll(b, &done, &am) == 0 && done == 1 && am == 1.5);
 }
 
 static void launch_error_keeps_tasks() {

@@ -33,10 +33,14 @@ def test_descriptor_is_32_bytes():
     assert ctypes.sizeof(hydroagg.hydro_subgrid_t) == 32
 
 
-def _desc(n=8, nf=11, level=0, reserved=0, u_in=0x1000, u_out=0x2000):
+STORED_8_11 = 11 * 14 ** 3 * 8      # bytes of an 8^3, F = 11 sub-grid with ghosts
+INTERIOR_8_11 = 11 * 8 ** 3 * 8
+
+
+def _desc(n=8, nf=11, level=0, out_layout=0, u_in=0x100000, u_out=0x10000000):
     a = (hydroagg.hydro_subgrid_t * 1)()
     a[0].u_in, a[0].u_out, a[0].n, a[0].nfields = u_in, u_out, n, nf
-    a[0].level, a[0].reserved = level, reserved
+    a[0].level, a[0].out_layout = level, out_layout
     return a
 
 
@@ -46,9 +50,15 @@ def _desc(n=8, nf=11, level=0, reserved=0, u_in=0x1000, u_out=0x2000):
     (dict(nf=7), 1, 0.1, 0.1),
     (dict(level=-1), 1, 0.1, 0.1),
     (dict(level=31), 1, 0.1, 0.1),
-    (dict(reserved=1), 1, 0.1, 0.1),
+    (dict(out_layout=2), 1, 0.1, 0.1),
+    (dict(out_layout=-1), 1, 0.1, 0.1),
     (dict(u_in=0), 1, 0.1, 0.1),
-    (dict(u_out=0x1000), 1, 0.1, 0.1),
+    (dict(u_out=0x100000), 1, 0.1, 0.1),
+    # u_out overlapping u_in by one double, either side, either layout
+    (dict(u_out=0x100000 + STORED_8_11 - 8), 1, 0.1, 0.1),
+    (dict(u_out=0x100000 - STORED_8_11 + 8), 1, 0.1, 0.1),
+    (dict(u_out=0x100000 - INTERIOR_8_11 + 8, out_layout=1), 1, 0.1, 0.1),
+    (dict(u_out=0x100008), 1, 0.1, 0.1),
     (dict(), -1, 0.1, 0.1),
     (dict(), 1, -0.1, 0.1),
     (dict(), 1, float("nan"), 0.1),

@@ -128,7 +128,8 @@ def _pool(dev, count=24, seed=620):
     return pool, tensors, Us, Ls, Ns
 
 
-def test_serving_loop_results_match_alone(dev):
+@pytest.mark.parametrize("layout", [hydroagg.OUT_STORED, hydroagg.OUT_INTERIOR])
+def test_serving_loop_results_match_alone(dev, layout):
     pool, keep, Us, Ls, Ns = _pool(dev)
     rng = np.random.default_rng(7)
     ntask = 90
@@ -136,7 +137,8 @@ def test_serving_loop_results_match_alone(dev):
     arrival = np.cumsum(rng.exponential(50.0, ntask))          # 20k tasks/s
     dx = 0.5
     dt = 1e-4
-    sizes = {8: 14 ** 3, 12: 18 ** 3, 16: 22 ** 3}
+    inner_only = layout == hydroagg.OUT_INTERIOR
+    sizes = {N: (N if inner_only else N + 6) ** 3 for N in (8, 12, 16)}
     counts = {N: int(np.sum(np.array([Ns[s] for s in task]) == N)) for N in (8, 12, 16)}
     arenas = []
     for N in (8, 12, 16):
@@ -144,7 +146,8 @@ def test_serving_loop_results_match_alone(dev):
         arenas.append((torch.zeros(max(k, 1) * 11 * sizes[N], dtype=torch.float64, device=dev), k))
     lat, am, slabs, st = hydroagg.serve_run(pool, task, arrival, nfields=11, dt=dt, dx=dx,
                                             slab_arenas=arenas, max_width=16, timeout_us=50.0,
-                                            n_streams=2, keep_slabs=True, want_slabs=True)
+                                            n_streams=2, keep_slabs=True, want_slabs=True,
+                                            out_layout=layout)
     torch.cuda.synchronize()
     assert st["agg"]["launched"] == ntask and np.all(lat > 0)
     # compare each task's slab with the sub-grid stepped alone
@@ -154,12 +157,13 @@ def test_serving_loop_results_match_alone(dev):
     for i in range(ntask):
         s = int(task[i])
         N = Ns[s]
-        M = N + 6
+        E = N if inner_only else N + 6
         off = (int(slabs[i]) - base[N]) // 8
-        out = arena_host[N][off:off + 11 * M ** 3].reshape(11, M, M, M)
+        out = arena_host[N][off:off + 11 * E ** 3].reshape(11, E, E, E)
         ref, ref_a = alone(Us[s][None], dt, dx, levels=[Ls[s]])
         inner = (slice(None), slice(3, 3 + N), slice(3, 3 + N), slice(3, 3 + N))
-        assert np.array_equal(out[inner], ref[0][inner]), i
+        got = out if inner_only else out[inner]
+        assert np.array_equal(got, ref[0][inner]), i
         assert am[i] == ref_a[0]
         checked += 1
     assert checked == ntask

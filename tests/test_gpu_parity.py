@@ -185,3 +185,49 @@ def test_x_only_data_has_no_transverse_update_on_gpu(dev, oracle_mod):
         assert np.array_equal(I, np.broadcast_to(I[:, :, :1, :1, :], I.shape))
         assert not I[:, 2].any() and not I[:, 3].any()
         check(U, 0.002, 0.05, oracle_mod)
+
+
+def _step_layouts(U, levels, dt, dx, dev, each=False):
+    """Step U once with stored-layout and once with interior-only outputs."""
+    count, nf, M = U.shape[0], U.shape[1], U.shape[2]
+    n = M - 6
+    u_in = torch.from_numpy(U).to(dev)
+    a = u_in.clone()
+    b = torch.full((count, nf, n, n, n), float("nan"), dtype=torch.float64, device=dev)
+    am_a = torch.zeros(count, dtype=torch.float64, device=dev)
+    am_b = torch.zeros(count, dtype=torch.float64, device=dev)
+    step = hydroagg.hydro_step_each if each else hydroagg.hydro_step
+    step(hydroagg.subgrids(u_in, a, levels=levels), dt, dx, am_a)
+    step(hydroagg.subgrids(u_in, b, levels=levels), dt, dx, am_b)
+    torch.cuda.synchronize()
+    return a.cpu().numpy(), b.cpu().numpy(), am_a.cpu().numpy(), am_b.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,nf,count,each", [(8, 11, 37, False), (8, 6, 5, False), (12, 11, 11, False),
+                                             (12, 6, 3, False), (16, 11, 9, False),
+                                             (16, 6, 2, True), (8, 11, 3, True)])
+def test_interior_layout_matches_stored_layout(dev, n, nf, count, each):
+    U = workloads.random_smooth(count, n=n, nfields=nf, seed=700 + n + nf + count)
+    levels = [s % 3 for s in range(count)]
+    print(f"layouts: n={n} F={nf} count={count} each={each}", flush=True)
+    a, b, am_a, am_b = _step_layouts(U, levels, 2e-3, 0.05, dev, each=each)
+    assert np.array_equal(interior(a, n), b)           # every element written, bitwise
+    assert np.array_equal(am_a, am_b)
+    g = ghost_mask(n)
+    assert np.array_equal(a[:, :, g], U[:, :, g])
+
+
+def test_layouts_mixed_in_one_batch(dev):
+    n, nf, count = 8, 11, 24
+    U = workloads.random_smooth(count, n=n, nfields=nf, seed=777)
+    u_in = torch.from_numpy(U).to(dev)
+    a = u_in[:12].clone()
+    b = torch.zeros((12, nf, n, n, n), dtype=torch.float64, device=dev)
+    batch = hydroagg.concat(hydroagg.subgrids(u_in[:12], a), hydroagg.subgrids(u_in[12:], b))
+    amax = torch.zeros(count, dtype=torch.float64, device=dev)
+    hydroagg.hydro_step(batch, 1e-3, 0.05, amax)
+    torch.cuda.synchronize()
+    ref, ref_a = run_gpu(U, 1e-3, 0.05)
+    assert np.array_equal(a.cpu().numpy(), ref[:12])
+    assert np.array_equal(b.cpu().numpy(), interior(ref[12:], n))
+    assert np.array_equal(amax.cpu().numpy(), ref_a)
