@@ -291,6 +291,19 @@ def main():
     value = cells / (ms * 1e-3)
     log(f"aggregated: {ms * 1e3:.1f} us/step, {value / 1e9:.3f} G cell-updates/s")
 
+    # ---- the kernel's own duration: an event pair around every launch -------
+    # (a separate pass, so the markers do not touch the timed region above;
+    # the graph holds this one kernel, so the pair brackets exactly it)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    for a_, b_ in ev:
+        a_.record(stream)
+        plan.graph(dt, dx, amax, stream)
+        b_.record(stream)
+    torch.cuda.synchronize()
+    kernel_ms = statistics.mean(a_.elapsed_time(b_) for a_, b_ in ev)
+    log(f"kernel duration (per-launch events): {kernel_ms * 1e3:.1f} us")
+
     # ---- the same step writing interior-only outputs (reported beside) -----
     interior_ms = None
     if args.interior_leg:
@@ -337,8 +350,8 @@ def main():
         log(f"device copy of {u_in.numel() * 8 / 1e9:.2f} GB: {copy_ms * 1e3:.1f} us, {copy_gbs:.0f} GB/s")
 
     floor_b, tile_b = bytes_per_subgrid(n, nf)
-    achieved = tile_b * count / (ms * 1e-3) / 1e9
-    achieved_floor = floor_b * count / (ms * 1e-3) / 1e9
+    achieved = tile_b * count / (kernel_ms * 1e-3) / 1e9
+    achieved_floor = floor_b * count / (kernel_ms * 1e-3) / 1e9
     version = hydroagg.version()
     workload_name = f"{count}x{n}^3 F={nf}"
     roofline = {
@@ -353,6 +366,9 @@ def main():
         "algorithmic_bytes_per_launch": tile_b * count,
         "bytes_definition": "stored (n+6)^3 tile read once + interior n^3 written once, 8 B x F per cell",
         "achieved_floor_gbs": round(achieved_floor, 1),
+        "kernel_ms": round(kernel_ms, 5),
+        "timing": "achieved = algorithmic bytes / mean duration of the kernel, HIP events "
+                  "around each of --steps launches on the launch stream",
         "floor_bytes_per_launch": floor_b * count,
         "measured_copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
     }
