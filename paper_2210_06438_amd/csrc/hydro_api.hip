@@ -21,6 +21,7 @@
 #include "../../include/hydroagg.h"
 #include "hydro_kernel.hpp"
 #include "hydro_lds8.hpp"
+#include "hydro_q4.hpp"
 
 using hydro::ArgDescs;
 using hydro::DevDesc;
@@ -133,9 +134,16 @@ int validate(const hydro_subgrid_t* sg, int32_t count, double dt, double dx) {
 }
 
 // Grid of the block kernel for n sub-grids of edge N.
+// Work-groups per sub-grid of edge N: one 8^3 block each for 8 and 16, and
+// for 12 seven groups of four 4^3 blocks.
+template <int N>
+constexpr int groups_per_subgrid() {
+  return N == 12 ? hydro::Q4::kGroups : hydro::Blocks<N + 6>::kPerSubgrid;
+}
+
 template <int N>
 int block_grid(int n) {
-  constexpr int B = hydro::Blocks<N + 6>::kPerSubgrid;
+  constexpr int B = groups_per_subgrid<N>();
   return B == 1 ? n : ((n + 7) / 8) * 8 * B;
 }
 
@@ -143,14 +151,18 @@ template <int N, int F>
 int launch_table(const DevDesc* table, int n, double dt, double dx, double* amax,
                  hipStream_t stream) {
   if (n <= 0) return HYDRO_OK;
-  constexpr int B = hydro::Blocks<N + 6>::kPerSubgrid;
+  constexpr int B = groups_per_subgrid<N>();
   if (B > 1 && amax) {
     hipLaunchKernelGGL(hydro::amax_zero_table, dim3((n + 255) / 256), dim3(256), 0, stream,
                        table, n, amax);
     HIP_TRY(hipGetLastError());
   }
-  hipLaunchKernelGGL((hydro::hydro_lds8_kernel<F, N + 6>), dim3(block_grid<N>(n)),
-                     dim3(hydro::Lds8::kThreads), 0, stream, table, n, dt, dx, amax);
+  if constexpr (N == 12)
+    hipLaunchKernelGGL((hydro::hydro_q4_kernel<F>), dim3(block_grid<N>(n)),
+                       dim3(hydro::Q4::kThreads), 0, stream, table, n, dt, dx, amax);
+  else
+    hipLaunchKernelGGL((hydro::hydro_lds8_kernel<F, N + 6>), dim3(block_grid<N>(n)),
+                       dim3(hydro::Lds8::kThreads), 0, stream, table, n, dt, dx, amax);
   HIP_TRY(hipGetLastError());
   return HYDRO_OK;
 }
@@ -159,13 +171,17 @@ template <int N, int F>
 int launch_args(const ArgDescs& a, int n, double dt, double dx, double* amax,
                 hipStream_t stream) {
   if (n <= 0) return HYDRO_OK;
-  constexpr int B = hydro::Blocks<N + 6>::kPerSubgrid;
+  constexpr int B = groups_per_subgrid<N>();
   if (B > 1 && amax) {
     hipLaunchKernelGGL(hydro::amax_zero_args, dim3(1), dim3(64), 0, stream, a, n, amax);
     HIP_TRY(hipGetLastError());
   }
-  hipLaunchKernelGGL((hydro::hydro_lds8_arg_kernel<F, N + 6>), dim3(n * B),
-                     dim3(hydro::Lds8::kThreads), 0, stream, a, dt, dx, amax);
+  if constexpr (N == 12)
+    hipLaunchKernelGGL((hydro::hydro_q4_arg_kernel<F>), dim3(n * B),
+                       dim3(hydro::Q4::kThreads), 0, stream, a, dt, dx, amax);
+  else
+    hipLaunchKernelGGL((hydro::hydro_lds8_arg_kernel<F, N + 6>), dim3(n * B),
+                       dim3(hydro::Lds8::kThreads), 0, stream, a, dt, dx, amax);
   HIP_TRY(hipGetLastError());
   return HYDRO_OK;
 }

@@ -1,14 +1,15 @@
 // hydro_lds8.hpp -- the gfx950 kernel of the aggregated sub-grid hydro step:
 // every needed input byte read from HBM once, direction sums kept on chip.
 //
-// Unit of work: an 8^3 block.  An 8^3 sub-grid is one block; 16^3 and 12^3
-// sub-grids are 8 blocks each, at block origins {0, n-8} per axis inside the
-// parent's stored array, so a block's ghost cells are simply the parent's
-// neighbouring cells and every block computes exactly what the whole
-// sub-grid would.  For n = 12 the blocks overlap by 4 cells; the second block
-// of an axis writes only its last 4.  One launch (per shape class) steps every
-// block of every sub-grid of a batch (the paper's explicit aggregation,
-// Section V-D).
+// Unit of work: an 8^3 block.  An 8^3 sub-grid is one block; a 16^3
+// sub-grid is 8 blocks, at block origins {0, 8} per axis inside the parent's
+// stored array, so a block's ghost cells are simply the parent's neighbouring
+// cells and every block computes exactly what the whole sub-grid would.  (The
+// geometry also covers n = 12 with origins {0, 4}, where the blocks overlap
+// and the second block of an axis writes only its last 4 cells; 12^3
+// sub-grids are stepped as 27 disjoint 4^3 blocks by hydro_q4.hpp instead.)
+// One launch (per shape class) steps every block of every sub-grid of a batch
+// (the paper's explicit aggregation, Section V-D).
 //
 // One work-group of 192 lanes steps one block: wave 0 owns the 64 lines
 // along x, wave 1 the lines along y, wave 2 the lines along z (one lane per

@@ -1,0 +1,308 @@
+// hydro_q4.hpp -- 12^3 sub-grids as 27 disjoint 4^3 blocks, four blocks per
+// work-group.
+//
+// 12 = 3 x 4, so the blocks tile the interior exactly: nothing is computed
+// twice (8^3 blocks of a 12^3 sub-grid would overlap and recompute 2.37x the
+// cells).  The step of one block is the step of hydro_lds8.hpp on a 4^3
+// interior with its 3-deep halo (a 10^3 frame inside the parent's stored
+// 18^3 array): the same reconstruction, flux and update code, marched along
+// lines of 10 stored cells.  A work-group of 192 lanes steps 4 blocks of one
+// sub-grid: wave 0 marches the x lines of all four (4 x 16 lanes), wave 1 the
+// y lines, wave 2 the z lines.  A sub-grid's 27 blocks (plus one idle slot)
+// are 7 work-groups whose indices are equal modulo 8, so they run on one XCD
+// and share its L2 for their common halos.
+//
+// Direction sums as in hydro_lds8.hpp: exactly two LDS atomic adds onto zero
+// per cell (x and y lanes), the z lanes keep U - lambda dF_z.  Every block
+// owns all of its cells; amax is combined across blocks with an atomic max of
+// the bit pattern onto a slot zeroed before the launch.
+#pragma once
+
+#include "hydro_lds8.hpp"
+
+namespace hydro {
+
+struct Q4 {
+  static constexpr int N = 4;
+  static constexpr int M = 10;            // stored cells along a line
+  static constexpr int MP = 18;           // parent stored edge
+  static constexpr int NI = 12;           // parent interior edge
+  static constexpr int RS = 5;            // LDS row stride (4 cells + 1 pad)
+  static constexpr int PS = 21;           // LDS plane stride
+  static constexpr int QS = 4 * PS + 1;   // LDS block stride
+  static constexpr int P = 4 * QS;        // one field of a cell array: 4 blocks
+  static constexpr int kThreads = 192;
+  static constexpr int kBlocks = 27;
+  static constexpr int kGroups = 7;       // work-groups per sub-grid (28 slots)
+};
+
+__device__ __forceinline__ int q4cell(int q, int x, int y, int z) {
+  return q * Q4::QS + z * Q4::PS + y * Q4::RS + x;
+}
+
+// Stored offset (in the parent) of the frame of block `item` (0..26); the
+// idle 28th slot repeats block 26 (its results are not stored).
+__device__ __forceinline__ int q4_org(int item, int& bx, int& by, int& bz) {
+  item = item < Q4::kBlocks ? item : Q4::kBlocks - 1;
+  bx = item % 3;
+  by = (item / 3) % 3;
+  bz = item / 9;
+  return ((4 * bz) * Q4::MP + 4 * by) * Q4::MP + 4 * bx;
+}
+
+// Interior shares of NF consecutive fields of the four blocks: element j of
+// a lane is e = t + j*192 of the fields stacked [f][q][z][y][x].
+template <int NF>
+struct Share4 {
+  static constexpr int K = (NF * 256 + Q4::kThreads - 1) / Q4::kThreads;
+  double v[K];
+};
+
+template <int NF>
+__device__ __forceinline__ void q4_load_share(const double* __restrict__ src, int group, int t,
+                                              Share4<NF>& sh) {
+  constexpr int K = Share4<NF>::K;
+  constexpr int REM = NF * 256 - (K - 1) * Q4::kThreads;
+  asm volatile("" : "+v"(t));   // recompute indices here (see load_share)
+  const gcptr g = as_global(src);
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int e = t + j * Q4::kThreads;
+    if (j + 1 < K || REM == Q4::kThreads || e < NF * 256) {
+      const int f = e >> 8, q = (e >> 6) & 3, x = e & 3, y = (e >> 2) & 3, z = (e >> 4) & 3;
+      int bx, by, bz;
+      const int org = q4_org(4 * group + q, bx, by, bz);
+      sh.v[j] = g[f * Frame<Q4::MP>::FS + org + Frame<Q4::MP>::cell(x, y, z)];
+    }
+  }
+}
+
+template <int NF>
+__device__ __forceinline__ void q4_store_share(double* lds, int t, const Share4<NF>& sh) {
+  constexpr int K = Share4<NF>::K;
+  constexpr int REM = NF * 256 - (K - 1) * Q4::kThreads;
+  asm volatile("" : "+v"(t));
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int e = t + j * Q4::kThreads;
+    if (j + 1 < K || REM == Q4::kThreads || e < NF * 256) {
+      const int f = e >> 8, q = (e >> 6) & 3, x = e & 3, y = (e >> 2) & 3, z = (e >> 4) & 3;
+      lds[f * Q4::P + q4cell(q, x, y, z)] = sh.v[j];
+    }
+  }
+}
+
+// The six ghost positions (0, 1, 2, 7, 8, 9) of this lane's line.
+template <int NF>
+__device__ __forceinline__ void q4_load_ghosts(const double* __restrict__ src, int gbase,
+                                               int gstride, double (&g)[NF][6]) {
+  const gcptr p = as_global(src) + gbase;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int i = j < 3 ? j : j + Q4::N;
+      g[f][j] = p[f * Frame<Q4::MP>::FS + i * gstride];
+    }
+  }
+}
+
+template <int F>
+__device__ __forceinline__ void q4_step(const DevDesc& d, int group, double dt, double dx,
+                                        double* __restrict__ amax_out) {
+  constexpr int M = Q4::M;
+  constexpr int N = Q4::N;
+  constexpr long FS = Frame<Q4::MP>::FS;
+  constexpr int P = Q4::P;
+  constexpr int NP = F - 5;
+  constexpr int NT = NP > 5 ? NP : 5;
+  __shared__ double tin[NT * P];
+  __shared__ double acc[5 * P];
+  __shared__ double held[5 * P];
+  __shared__ double red[3];
+
+  const int t = threadIdx.x;
+  const int dir = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int l = t & 63;
+  const int q = l >> 4;                  // block slot of this lane
+  const int a = l & 3, b = (l >> 2) & 3; // transverse coordinates of its line
+  const int item = 4 * group + q;
+  const bool stores = item < Q4::kBlocks;
+  int bx, by, bz;
+  const int org = q4_org(item, bx, by, bz);
+  const double ex = dir == 0 ? 1.0 : 0.0;
+  const double ey = dir == 1 ? 1.0 : 0.0;
+  const double ez = dir == 2 ? 1.0 : 0.0;
+  const int lbase = dir == 0 ? q4cell(q, 0, a, b) : dir == 1 ? q4cell(q, a, 0, b) : q4cell(q, a, b, 0);
+  const int lstride = dir == 0 ? 1 : dir == 1 ? Q4::RS : Q4::PS;
+  const int gbase = org + Frame<Q4::MP>::line(dir, a, b, 0);
+  const int gstride = Frame<Q4::MP>::stride(dir);
+  const double lambda = dt / ldexp(dx, -d.level);
+  const double* __restrict__ uin = d.u_in;
+  // z lanes write column (a, b) of their block, all four cells
+  const bool compact = d.compact != 0;
+  double* __restrict__ uout = d.u_out;
+  const long ofs = compact ? (long)Q4::NI * Q4::NI * Q4::NI : FS;
+  const int ostride = compact ? Q4::NI * Q4::NI : Q4::MP * Q4::MP;
+  const int obase = compact ? ((4 * bz) * Q4::NI + 4 * by + b) * Q4::NI + 4 * bx + a
+                            : org + Frame<Q4::MP>::line(2, a, b, kGhost);
+
+  // ---- stage the hydro core ---------------------------------------------
+  {
+    Share4<5> sh;
+    q4_load_share<5>(uin, group, t, sh);
+    for (int i = t; i < 5 * P; i += Q4::kThreads) acc[i] = 0.0;
+    q4_store_share<5>(tin, t, sh);
+  }
+  double g[5][6];
+  q4_load_ghosts<5>(uin, gbase, gstride, g);
+  __syncthreads();
+
+  double smax = 0.0;
+  double wm[N + 1], wp[N + 1];
+  {
+    Recon<5> rc;
+    double Fprev[5];
+    double qv[5], Wm[5], Wp[5];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      double Ui[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k)
+        Ui[k] = (i >= kGhost && i < kGhost + N) ? tin[k * P + lbase + (i - kGhost) * lstride]
+                                                : g[k][i < kGhost ? i : i - N];
+      to_prim(Ui, qv);
+      switch (i) {
+        case 0: rc.step<0>(qv, Wm, Wp); break;
+        case 1: rc.step<1>(qv, Wm, Wp); break;
+        case 2: rc.step<2>(qv, Wm, Wp); break;
+        case 3: rc.step<3>(qv, Wm, Wp); break;
+        case 4: rc.step<4>(qv, Wm, Wp); break;
+        case 5: rc.step<5>(qv, Wm, Wp); break;
+        default: rc.step<6>(qv, Wm, Wp); break;
+      }
+      if (i >= 5) {
+        double Fh[5];
+        const int face = i - 5;
+        smax = fmax(smax, core_flux(Wm, Wp, ex, ey, ez, Fh, wm[face], wp[face]));
+        if (i >= 6) {
+          const int cell = lbase + (i - 6) * lstride;
+          if (dir == 2) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+              held[k * P + cell] = tin[k * P + cell] - lambda * (Fh[k] - Fprev[k]);
+          } else {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) atomicAdd(&acc[k * P + cell], Fh[k] - Fprev[k]);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Fprev[k] = Fh[k];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+
+  // ---- all passive fields in one burst ----------------------------------
+  Share4<NP> ps;
+  double pg[NP][6];
+  q4_load_share<NP>(uin + 5 * FS, group, t, ps);
+  q4_load_ghosts<NP>(uin + 5 * FS, gbase, gstride, pg);
+  __syncthreads();   // hydro sums complete; tin free
+  if (dir == 2) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        const int cell = k * P + lbase + c * lstride;
+        if (stores)
+          __builtin_nontemporal_store(held[cell] - lambda * acc[cell],
+                                      &as_global(uout)[k * ofs + obase + c * ostride]);
+        acc[cell] = 0.0;
+      }
+    }
+  }
+  q4_store_share<NP>(tin, t, ps);
+  __syncthreads();   // tin holds every passive field; accumulator clear
+
+  // ---- passive fields, one at a time, from LDS ---------------------------
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    double L[N];
+    Recon<1> rc;
+    double Fprev = 0.0;
+    double qv[1], Wm[1], Wp[1];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      qv[0] = (i >= kGhost && i < kGhost + N) ? tin[p * P + lbase + (i - kGhost) * lstride]
+                                              : pg[p][i < kGhost ? i : i - N];
+      switch (i) {
+        case 0: rc.step<0>(qv, Wm, Wp); break;
+        case 1: rc.step<1>(qv, Wm, Wp); break;
+        case 2: rc.step<2>(qv, Wm, Wp); break;
+        case 3: rc.step<3>(qv, Wm, Wp); break;
+        case 4: rc.step<4>(qv, Wm, Wp); break;
+        case 5: rc.step<5>(qv, Wm, Wp); break;
+        default: rc.step<6>(qv, Wm, Wp); break;
+      }
+      if (i >= 5) {
+        const double Fh = wm[i - 5] * Wm[0] + wp[i - 5] * Wp[0];
+        if (i >= 6) {
+          const int cell = lbase + (i - 6) * lstride;
+          if (dir == 2)
+            L[i - 6] = tin[p * P + cell] - lambda * (Fh - Fprev);
+          else
+            atomicAdd(&acc[(p % 2) * P + cell], Fh - Fprev);
+        }
+        Fprev = Fh;
+      }
+    }
+    // Two accumulator regions alternate, as in hydro_lds8.hpp.
+    __syncthreads();
+    if (dir == 2) {
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        const int cell = (p % 2) * P + lbase + c * lstride;
+        if (stores)
+          __builtin_nontemporal_store(L[c] - lambda * acc[cell],
+                                      &as_global(uout)[(5 + p) * ofs + obase + c * ostride]);
+        acc[cell] = 0.0;
+      }
+    }
+  }
+
+  if (amax_out) {
+    smax = wave_max(smax);
+    if (l == 0) red[dir] = smax;
+    __syncthreads();
+    if (t == 0) {
+      const double m = fmax(fmax(red[0], red[1]), red[2]);
+      atomicMax(reinterpret_cast<unsigned long long*>(&amax_out[d.index]),
+                (unsigned long long)__double_as_longlong(m));
+    }
+  }
+}
+
+// Table form: the 7 work-groups of sub-grid s have indices equal modulo 8.
+// The grid is ceil(count/8)*8*7.
+template <int F>
+__global__ void __launch_bounds__(Q4::kThreads, 2)
+    hydro_q4_kernel(const DevDesc* __restrict__ table, int count, double dt, double dx,
+                    double* __restrict__ amax_out) {
+  constexpr int B = Q4::kGroups;
+  const int w = blockIdx.x;
+  const int s = (w / (8 * B)) * 8 + (w & 7);
+  const int group = (w >> 3) % B;
+  if (s >= count) return;
+  const DevDesc d = table[s];
+  q4_step<F>(d, group, dt, dx, amax_out);
+}
+
+template <int F>
+__global__ void __launch_bounds__(Q4::kThreads, 2)
+    hydro_q4_arg_kernel(ArgDescs descs, double dt, double dx, double* __restrict__ amax_out) {
+  const DevDesc d = descs.d[blockIdx.x / Q4::kGroups];
+  q4_step<F>(d, blockIdx.x % Q4::kGroups, dt, dx, amax_out);
+}
+
+}  // namespace hydro
