@@ -43,9 +43,9 @@ def bytes_per_subgrid(n, nf):
     return floor, tile
 
 
-def measured_traffic(version, workload):
+def measured_traffic(version, workload, kernel):
     """HBM bytes per launch from the committed rocprofv3 counter record, or
-    None when that record was taken on another build of the kernel."""
+    None when that record was taken on another build or another kernel."""
     path = os.path.join(ROOT, "paper_2210_06438_amd", "measured_traffic.json")
     try:
         with open(path) as f:
@@ -53,6 +53,8 @@ def measured_traffic(version, workload):
     except (OSError, ValueError):
         return None
     if rec.get("kernel_version") != version or rec.get("workload") != workload:
+        return None
+    if kernel.split("<")[0] not in rec.get("kernel", ""):
         return None
     return int(rec["traffic_bytes_per_launch"])
 
@@ -235,6 +237,10 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--serve-budget-mb", type=float, default=64.0)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-width leg")
+    ap.add_argument("--tile-tune", type=int, default=1,
+                    help="1: choose every class's tile with the autotuner first (else the defaults)")
+    ap.add_argument("--tile-count", type=int, default=512,
+                    help="sub-grids per class in the tile sweep")
     ap.add_argument("--interior-leg", type=int, default=1,
                     help="1: also time the headline step with interior-only outputs")
     ap.add_argument("--learned-splits", type=int, default=10)
@@ -256,6 +262,14 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     dev = torch.device("cuda:0")
     hydroagg.lib()   # fail loudly if the HIP library is missing
+
+    # ---- tile of every shape class, from the autotuner ---------------------
+    from paper_2210_06438_amd import tune
+    tiles = None
+    if args.tile_tune:
+        recs, best = tune.tile_sweep(count=args.tile_count, dev=dev, log=log)
+        tiles = {"chosen": {f"{k[0]}^3 F={k[1]}": v for k, v in best.items()}, "records": recs,
+                 "batch": args.tile_count}
 
     count, n, nf = args.count, args.n, args.nfields
     dx = 1.0 / 64
@@ -354,14 +368,16 @@ def main():
     achieved_floor = floor_b * count / (kernel_ms * 1e-3) / 1e9
     version = hydroagg.version()
     workload_name = f"{count}x{n}^3 F={nf}"
+    kname = (f"hydro_lds8_kernel<{nf},{n + 2 * GHOST}>" if hydroagg.get_tile(n, nf) == 8
+             else f"hydro_q4_kernel<{nf},{n + 2 * GHOST}>")
     roofline = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(version, workload_name),
-        "kernel": f"hydro_lds8_kernel<{nf},{n + 2 * GHOST}>",
+        "traffic": measured_traffic(version, workload_name, kname),
+        "kernel": kname,
         "kernel_version": version,
         "algorithmic_bytes_per_launch": tile_b * count,
         "bytes_definition": "stored (n+6)^3 tile read once + interior n^3 written once, 8 B x F per cell",
@@ -425,6 +441,7 @@ def main():
             "workload": f"{count} sub-grids of {n}^3 (+3 ghost layers), {nf} FP64 fields, "
                         "random smooth state, one aggregated hipGraph launch per step",
             "subgrids": count, "n": n, "nfields": nf, "dx": dx, "cfl": 0.4,
+            "tile": hydroagg.get_tile(n, nf),
         },
         "per_subgrid_launch": None if each_ms is None else {
             "value": round(cells / (each_ms * 1e-3), 1), "ms_per_step": round(each_ms, 4),
@@ -438,6 +455,7 @@ def main():
         "uneven": uneven,
         "serving": serving,
         "learned_width": learned_res,
+        "tile_autotune": tiles,
     }
     plan.close()
     print(json.dumps(out), flush=True)

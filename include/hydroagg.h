@@ -68,6 +68,22 @@ typedef struct {
 } hydro_subgrid_t;
 
 /*
+ * hydro_set_tile / hydro_get_tile -- the block ("tile") a sub-grid of class
+ * (n, nfields) is stepped as: tile 8 = 8^3 blocks (one per 8^3 sub-grid, 8
+ * per 16^3, 8 overlapping ones per 12^3), tile 4 = disjoint 4^3 blocks, four
+ * per work-group.  Both compute every face from the same cells, so results
+ * agree to rounding (the two kernels may contract the same expressions
+ * differently); for a fixed tile they are bitwise reproducible and
+ * independent of the batch.  The choice is made by the autotuner
+ * (paper_2210_06438_amd/tune.py).  Defaults:
+ * 8 for n = 8 and 16, 4 for n = 12.  Process-wide; read at every launch; a
+ * plan re-captures its graph after a change.  Errors: HYDRO_EINVAL for an
+ * unsupported class, a tile other than 4 or 8, or tile == NULL.
+ */
+int hydro_set_tile(int32_t n, int32_t nfields, int32_t tile);
+int hydro_get_tile(int32_t n, int32_t nfields, int32_t *tile);
+
+/*
  * hydro_step -- one stage for `count` sub-grids (paper Section IV-B), as one
  * aggregated launch per (n, nfields) class present in the batch.
  *   sg       host array of `count` descriptors (copied before return).

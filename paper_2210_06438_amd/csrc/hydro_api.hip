@@ -15,6 +15,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -133,35 +134,37 @@ int validate(const hydro_subgrid_t* sg, int32_t count, double dt, double dx) {
   return HYDRO_OK;
 }
 
-// Grid of the block kernel for n sub-grids of edge N.
-// Work-groups per sub-grid of edge N: one 8^3 block each for 8 and 16, and
-// for 12 seven groups of four 4^3 blocks.
+// Tile of each shape class: the edge of the blocks a sub-grid is stepped as
+// (8: hydro_lds8.hpp, 4: hydro_q4.hpp).  Set by hydro_set_tile (from the
+// autotuner); read at every launch.  g_tile_epoch lets captured plans notice
+// a change.
+std::atomic<int> g_tile[kClasses] = {{8}, {8}, {4}, {4}, {8}, {8}};
+std::atomic<uint64_t> g_tile_epoch{0};
+
+// Work-groups per sub-grid of edge N with tile T.
 template <int N>
-constexpr int groups_per_subgrid() {
-  return N == 12 ? hydro::Q4::kGroups : hydro::Blocks<N + 6>::kPerSubgrid;
+int groups_per_subgrid(int tile) {
+  return tile == 4 ? hydro::Q4Grid<N + 6>::kGroups : hydro::Blocks<N + 6>::kPerSubgrid;
 }
 
-template <int N>
-int block_grid(int n) {
-  constexpr int B = groups_per_subgrid<N>();
-  return B == 1 ? n : ((n + 7) / 8) * 8 * B;
-}
+int grid_for(int n, int B) { return B == 1 ? n : ((n + 7) / 8) * 8 * B; }
 
 template <int N, int F>
 int launch_table(const DevDesc* table, int n, double dt, double dx, double* amax,
                  hipStream_t stream) {
   if (n <= 0) return HYDRO_OK;
-  constexpr int B = groups_per_subgrid<N>();
+  const int tile = g_tile[class_of(N, F)].load(std::memory_order_relaxed);
+  const int B = groups_per_subgrid<N>(tile);
   if (B > 1 && amax) {
     hipLaunchKernelGGL(hydro::amax_zero_table, dim3((n + 255) / 256), dim3(256), 0, stream,
                        table, n, amax);
     HIP_TRY(hipGetLastError());
   }
-  if constexpr (N == 12)
-    hipLaunchKernelGGL((hydro::hydro_q4_kernel<F>), dim3(block_grid<N>(n)),
+  if (tile == 4)
+    hipLaunchKernelGGL((hydro::hydro_q4_kernel<F, N + 6>), dim3(grid_for(n, B)),
                        dim3(hydro::Q4::kThreads), 0, stream, table, n, dt, dx, amax);
   else
-    hipLaunchKernelGGL((hydro::hydro_lds8_kernel<F, N + 6>), dim3(block_grid<N>(n)),
+    hipLaunchKernelGGL((hydro::hydro_lds8_kernel<F, N + 6>), dim3(grid_for(n, B)),
                        dim3(hydro::Lds8::kThreads), 0, stream, table, n, dt, dx, amax);
   HIP_TRY(hipGetLastError());
   return HYDRO_OK;
@@ -171,13 +174,14 @@ template <int N, int F>
 int launch_args(const ArgDescs& a, int n, double dt, double dx, double* amax,
                 hipStream_t stream) {
   if (n <= 0) return HYDRO_OK;
-  constexpr int B = groups_per_subgrid<N>();
+  const int tile = g_tile[class_of(N, F)].load(std::memory_order_relaxed);
+  const int B = groups_per_subgrid<N>(tile);
   if (B > 1 && amax) {
     hipLaunchKernelGGL(hydro::amax_zero_args, dim3(1), dim3(64), 0, stream, a, n, amax);
     HIP_TRY(hipGetLastError());
   }
-  if constexpr (N == 12)
-    hipLaunchKernelGGL((hydro::hydro_q4_arg_kernel<F>), dim3(n * B),
+  if (tile == 4)
+    hipLaunchKernelGGL((hydro::hydro_q4_arg_kernel<F, N + 6>), dim3(n * B),
                        dim3(hydro::Q4::kThreads), 0, stream, a, dt, dx, amax);
   else
     hipLaunchKernelGGL((hydro::hydro_lds8_arg_kernel<F, N + 6>), dim3(n * B),
@@ -304,6 +308,7 @@ struct hydro_plan {
   hipGraphExec_t exec = nullptr;
   double g_dt = -1.0, g_dx = -1.0;
   double* g_amax = nullptr;
+  uint64_t g_tiles = ~0ull;  // tile epoch of the captured graph
 };
 
 namespace {
@@ -413,7 +418,8 @@ int hydro_plan_launch_graph(hydro_plan_t* p, double dt, double dx, double* amax_
   int rc = validate(nullptr, 0, dt, dx);
   if (rc) return rc;
   if (p->count == 0) return HYDRO_OK;
-  if (!p->exec || p->g_dt != dt || p->g_dx != dx || p->g_amax != amax_dev) {
+  const uint64_t tiles = g_tile_epoch.load(std::memory_order_acquire);
+  if (!p->exec || p->g_dt != dt || p->g_dx != dx || p->g_amax != amax_dev || p->g_tiles != tiles) {
     // (re)capture one step on the plan's private stream
     if (p->exec) {
       (void)hipGraphExecDestroy(p->exec);
@@ -437,6 +443,7 @@ int hydro_plan_launch_graph(hydro_plan_t* p, double dt, double dx, double* amax_
     p->g_dt = dt;
     p->g_dx = dx;
     p->g_amax = amax_dev;
+    p->g_tiles = tiles;
   }
   HIP_TRY(hipGraphLaunch(p->exec, (hipStream_t)stream));
   return HYDRO_OK;
@@ -460,6 +467,25 @@ const char* hydro_last_error(void) { return g_err; }
 #ifndef HYDRO_SRC_HASH
 #define HYDRO_SRC_HASH "unknown"
 #endif
+int hydro_set_tile(int32_t n, int32_t nfields, int32_t tile) {
+  hydro::api::clear_error();
+  const int c = class_of(n, nfields);
+  if (c < 0) return fail(HYDRO_EINVAL, "unsupported n=%d nfields=%d", n, nfields);
+  if (tile != 4 && tile != 8) return fail(HYDRO_EINVAL, "tile %d (4 or 8)", tile);
+  g_tile[c].store(tile, std::memory_order_relaxed);
+  g_tile_epoch.fetch_add(1, std::memory_order_acq_rel);
+  return HYDRO_OK;
+}
+
+int hydro_get_tile(int32_t n, int32_t nfields, int32_t* tile) {
+  hydro::api::clear_error();
+  const int c = class_of(n, nfields);
+  if (c < 0) return fail(HYDRO_EINVAL, "unsupported n=%d nfields=%d", n, nfields);
+  if (!tile) return fail(HYDRO_EINVAL, "tile is NULL");
+  *tile = g_tile[c].load(std::memory_order_relaxed);
+  return HYDRO_OK;
+}
+
 const char* hydro_version(void) { return "hydroagg gfx950 src " HYDRO_SRC_HASH; }
 
 }  // extern "C"

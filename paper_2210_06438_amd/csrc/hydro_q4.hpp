@@ -1,16 +1,17 @@
-// hydro_q4.hpp -- 12^3 sub-grids as 27 disjoint 4^3 blocks, four blocks per
-// work-group.
+// hydro_q4.hpp -- sub-grids stepped as disjoint 4^3 blocks, four blocks per
+// work-group (the "4^3 tile"; hydro_lds8.hpp is the 8^3 tile).
 //
-// 12 = 3 x 4, so the blocks tile the interior exactly: nothing is computed
-// twice (8^3 blocks of a 12^3 sub-grid would overlap and recompute 2.37x the
-// cells).  The step of one block is the step of hydro_lds8.hpp on a 4^3
-// interior with its 3-deep halo (a 10^3 frame inside the parent's stored
-// 18^3 array): the same reconstruction, flux and update code, marched along
-// lines of 10 stored cells.  A work-group of 192 lanes steps 4 blocks of one
-// sub-grid: wave 0 marches the x lines of all four (4 x 16 lanes), wave 1 the
-// y lines, wave 2 the z lines.  A sub-grid's 27 blocks (plus one idle slot)
-// are 7 work-groups whose indices are equal modulo 8, so they run on one XCD
-// and share its L2 for their common halos.
+// Every edge n in {8, 12, 16} is a multiple of 4, so the blocks tile the
+// interior exactly: nothing is computed twice (8^3 blocks of a 12^3 sub-grid
+// overlap and recompute 2.37x the cells).  The step of one block is the step
+// of hydro_lds8.hpp on a 4^3 interior with its 3-deep halo (a 10^3 frame
+// inside the parent's stored (n+6)^3 array): the same reconstruction, flux and
+// update code, marched along lines of 10 stored cells, computing every face
+// from the same cells -- results agree with the 8^3 tile to rounding.  A work-group of 192 lanes steps 4 blocks of one sub-grid: wave 0
+// marches the x lines of all four (4 x 16 lanes), wave 1 the y lines, wave 2
+// the z lines.  A sub-grid's (n/4)^3 blocks (8, 27 or 64; padded to a multiple
+// of 4 with idle slots) are 2, 7 or 16 work-groups whose indices are equal
+// modulo 8, so they run on one XCD and share its L2 for their common halos.
 //
 // Direction sums as in hydro_lds8.hpp: exactly two LDS atomic adds onto zero
 // per cell (x and y lanes), the z lanes keep U - lambda dF_z.  Every block
@@ -25,29 +26,37 @@ namespace hydro {
 struct Q4 {
   static constexpr int N = 4;
   static constexpr int M = 10;            // stored cells along a line
-  static constexpr int MP = 18;           // parent stored edge
-  static constexpr int NI = 12;           // parent interior edge
   static constexpr int RS = 5;            // LDS row stride (4 cells + 1 pad)
   static constexpr int PS = 21;           // LDS plane stride
   static constexpr int QS = 4 * PS + 1;   // LDS block stride
   static constexpr int P = 4 * QS;        // one field of a cell array: 4 blocks
   static constexpr int kThreads = 192;
-  static constexpr int kBlocks = 27;
-  static constexpr int kGroups = 7;       // work-groups per sub-grid (28 slots)
+};
+
+// Geometry of the 4^3 tiling of a parent with stored edge MP.
+template <int MP>
+struct Q4Grid {
+  static constexpr int NI = MP - 2 * kGhost;       // parent interior edge
+  static constexpr int BA = NI / 4;                // blocks per axis
+  static constexpr int kBlocks = BA * BA * BA;
+  static constexpr int kGroups = (kBlocks + 3) / 4;  // work-groups per sub-grid
+  static_assert(NI % 4 == 0, "edge must be a multiple of 4");
 };
 
 __device__ __forceinline__ int q4cell(int q, int x, int y, int z) {
   return q * Q4::QS + z * Q4::PS + y * Q4::RS + x;
 }
 
-// Stored offset (in the parent) of the frame of block `item` (0..26); the
-// idle 28th slot repeats block 26 (its results are not stored).
+// Stored offset (in the parent) of the frame of block `item`; idle slots
+// past the last block repeat it (their results are not stored).
+template <int MP>
 __device__ __forceinline__ int q4_org(int item, int& bx, int& by, int& bz) {
-  item = item < Q4::kBlocks ? item : Q4::kBlocks - 1;
-  bx = item % 3;
-  by = (item / 3) % 3;
-  bz = item / 9;
-  return ((4 * bz) * Q4::MP + 4 * by) * Q4::MP + 4 * bx;
+  constexpr int BA = Q4Grid<MP>::BA;
+  item = item < Q4Grid<MP>::kBlocks ? item : Q4Grid<MP>::kBlocks - 1;
+  bx = item % BA;
+  by = (item / BA) % BA;
+  bz = item / (BA * BA);
+  return ((4 * bz) * MP + 4 * by) * MP + 4 * bx;
 }
 
 // Interior shares of NF consecutive fields of the four blocks: element j of
@@ -58,7 +67,7 @@ struct Share4 {
   double v[K];
 };
 
-template <int NF>
+template <int NF, int MP>
 __device__ __forceinline__ void q4_load_share(const double* __restrict__ src, int group, int t,
                                               Share4<NF>& sh) {
   constexpr int K = Share4<NF>::K;
@@ -71,8 +80,8 @@ __device__ __forceinline__ void q4_load_share(const double* __restrict__ src, in
     if (j + 1 < K || REM == Q4::kThreads || e < NF * 256) {
       const int f = e >> 8, q = (e >> 6) & 3, x = e & 3, y = (e >> 2) & 3, z = (e >> 4) & 3;
       int bx, by, bz;
-      const int org = q4_org(4 * group + q, bx, by, bz);
-      sh.v[j] = g[f * Frame<Q4::MP>::FS + org + Frame<Q4::MP>::cell(x, y, z)];
+      const int org = q4_org<MP>(4 * group + q, bx, by, bz);
+      sh.v[j] = g[f * Frame<MP>::FS + org + Frame<MP>::cell(x, y, z)];
     }
   }
 }
@@ -93,7 +102,7 @@ __device__ __forceinline__ void q4_store_share(double* lds, int t, const Share4<
 }
 
 // The six ghost positions (0, 1, 2, 7, 8, 9) of this lane's line.
-template <int NF>
+template <int NF, int MP>
 __device__ __forceinline__ void q4_load_ghosts(const double* __restrict__ src, int gbase,
                                                int gstride, double (&g)[NF][6]) {
   const gcptr p = as_global(src) + gbase;
@@ -102,17 +111,18 @@ __device__ __forceinline__ void q4_load_ghosts(const double* __restrict__ src, i
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       const int i = j < 3 ? j : j + Q4::N;
-      g[f][j] = p[f * Frame<Q4::MP>::FS + i * gstride];
+      g[f][j] = p[f * Frame<MP>::FS + i * gstride];
     }
   }
 }
 
-template <int F>
+template <int F, int MP>
 __device__ __forceinline__ void q4_step(const DevDesc& d, int group, double dt, double dx,
                                         double* __restrict__ amax_out) {
   constexpr int M = Q4::M;
   constexpr int N = Q4::N;
-  constexpr long FS = Frame<Q4::MP>::FS;
+  constexpr int NI = Q4Grid<MP>::NI;
+  constexpr long FS = Frame<MP>::FS;
   constexpr int P = Q4::P;
   constexpr int NP = F - 5;
   constexpr int NT = NP > 5 ? NP : 5;
@@ -127,35 +137,35 @@ __device__ __forceinline__ void q4_step(const DevDesc& d, int group, double dt, 
   const int q = l >> 4;                  // block slot of this lane
   const int a = l & 3, b = (l >> 2) & 3; // transverse coordinates of its line
   const int item = 4 * group + q;
-  const bool stores = item < Q4::kBlocks;
+  const bool stores = item < Q4Grid<MP>::kBlocks;
   int bx, by, bz;
-  const int org = q4_org(item, bx, by, bz);
+  const int org = q4_org<MP>(item, bx, by, bz);
   const double ex = dir == 0 ? 1.0 : 0.0;
   const double ey = dir == 1 ? 1.0 : 0.0;
   const double ez = dir == 2 ? 1.0 : 0.0;
   const int lbase = dir == 0 ? q4cell(q, 0, a, b) : dir == 1 ? q4cell(q, a, 0, b) : q4cell(q, a, b, 0);
   const int lstride = dir == 0 ? 1 : dir == 1 ? Q4::RS : Q4::PS;
-  const int gbase = org + Frame<Q4::MP>::line(dir, a, b, 0);
-  const int gstride = Frame<Q4::MP>::stride(dir);
+  const int gbase = org + Frame<MP>::line(dir, a, b, 0);
+  const int gstride = Frame<MP>::stride(dir);
   const double lambda = dt / ldexp(dx, -d.level);
   const double* __restrict__ uin = d.u_in;
   // z lanes write column (a, b) of their block, all four cells
   const bool compact = d.compact != 0;
   double* __restrict__ uout = d.u_out;
-  const long ofs = compact ? (long)Q4::NI * Q4::NI * Q4::NI : FS;
-  const int ostride = compact ? Q4::NI * Q4::NI : Q4::MP * Q4::MP;
-  const int obase = compact ? ((4 * bz) * Q4::NI + 4 * by + b) * Q4::NI + 4 * bx + a
-                            : org + Frame<Q4::MP>::line(2, a, b, kGhost);
+  const long ofs = compact ? (long)NI * NI * NI : FS;
+  const int ostride = compact ? NI * NI : MP * MP;
+  const int obase = compact ? ((4 * bz) * NI + 4 * by + b) * NI + 4 * bx + a
+                            : org + Frame<MP>::line(2, a, b, kGhost);
 
   // ---- stage the hydro core ---------------------------------------------
   {
     Share4<5> sh;
-    q4_load_share<5>(uin, group, t, sh);
+    q4_load_share<5, MP>(uin, group, t, sh);
     for (int i = t; i < 5 * P; i += Q4::kThreads) acc[i] = 0.0;
     q4_store_share<5>(tin, t, sh);
   }
   double g[5][6];
-  q4_load_ghosts<5>(uin, gbase, gstride, g);
+  q4_load_ghosts<5, MP>(uin, gbase, gstride, g);
   __syncthreads();
 
   double smax = 0.0;
@@ -206,8 +216,8 @@ __device__ __forceinline__ void q4_step(const DevDesc& d, int group, double dt, 
   // ---- all passive fields in one burst ----------------------------------
   Share4<NP> ps;
   double pg[NP][6];
-  q4_load_share<NP>(uin + 5 * FS, group, t, ps);
-  q4_load_ghosts<NP>(uin + 5 * FS, gbase, gstride, pg);
+  q4_load_share<NP, MP>(uin + 5 * FS, group, t, ps);
+  q4_load_ghosts<NP, MP>(uin + 5 * FS, gbase, gstride, pg);
   __syncthreads();   // hydro sums complete; tin free
   if (dir == 2) {
 #pragma unroll
@@ -283,26 +293,27 @@ __device__ __forceinline__ void q4_step(const DevDesc& d, int group, double dt, 
   }
 }
 
-// Table form: the 7 work-groups of sub-grid s have indices equal modulo 8.
-// The grid is ceil(count/8)*8*7.
-template <int F>
+// Table form: the B work-groups of sub-grid s have indices equal modulo 8.
+// The grid is ceil(count/8)*8*B.
+template <int F, int MP>
 __global__ void __launch_bounds__(Q4::kThreads, 2)
     hydro_q4_kernel(const DevDesc* __restrict__ table, int count, double dt, double dx,
                     double* __restrict__ amax_out) {
-  constexpr int B = Q4::kGroups;
+  constexpr int B = Q4Grid<MP>::kGroups;
   const int w = blockIdx.x;
   const int s = (w / (8 * B)) * 8 + (w & 7);
   const int group = (w >> 3) % B;
   if (s >= count) return;
   const DevDesc d = table[s];
-  q4_step<F>(d, group, dt, dx, amax_out);
+  q4_step<F, MP>(d, group, dt, dx, amax_out);
 }
 
-template <int F>
+template <int F, int MP>
 __global__ void __launch_bounds__(Q4::kThreads, 2)
     hydro_q4_arg_kernel(ArgDescs descs, double dt, double dx, double* __restrict__ amax_out) {
-  const DevDesc d = descs.d[blockIdx.x / Q4::kGroups];
-  q4_step<F>(d, blockIdx.x % Q4::kGroups, dt, dx, amax_out);
+  constexpr int B = Q4Grid<MP>::kGroups;
+  const DevDesc d = descs.d[blockIdx.x / B];
+  q4_step<F, MP>(d, blockIdx.x % B, dt, dx, amax_out);
 }
 
 }  // namespace hydro

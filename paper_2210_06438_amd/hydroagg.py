@@ -109,6 +109,10 @@ def lib() -> ctypes.CDLL:
                      "hydro_poll", "hydro_wait", "hydro_agg_stats", "hydro_agg_destroy",
                      "hydro_serve_run"):
             getattr(L, name).restype = ctypes.c_int
+        L.hydro_set_tile.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.hydro_set_tile.restype = ctypes.c_int
+        L.hydro_get_tile.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.hydro_get_tile.restype = ctypes.c_int
         L.hydro_last_error.argtypes = []
         L.hydro_last_error.restype = ctypes.c_char_p
         L.hydro_version.argtypes = []
@@ -137,6 +141,17 @@ def _stream(stream) -> int:
     if isinstance(stream, int):
         return stream
     return int(stream.cuda_stream)
+
+
+def set_tile(n, nfields, tile):
+    """Step sub-grids of class (n, nfields) as tile^3 blocks (4 or 8)."""
+    _check(lib().hydro_set_tile(int(n), int(nfields), int(tile)))
+
+
+def get_tile(n, nfields):
+    t = ctypes.c_int32()
+    _check(lib().hydro_get_tile(int(n), int(nfields), ctypes.byref(t)))
+    return int(t.value)
 
 
 def subgrids(u_in, u_out, levels=None, n=None, nfields=None):

@@ -1,5 +1,10 @@
-"""Exhaustive autotuner of the aggregation width, and the timing sweep that
-feeds the learned width model.
+"""Autotuners: the tile (block shape) of each shape class, and the
+aggregation width -- exhaustive, and the timing sweep that feeds the learned
+width model.
+
+Tile: tile_sweep() times one aggregated step of a batch of every (n, F)
+class with each tile (8^3 or 4^3 blocks; the same faces, results equal to
+rounding) and keeps the faster one (hydro_set_tile).
 
 A serving condition is (n, nfields, arrival rate).  For each condition the
 tuner replays the same seeded Poisson arrival sequence through the serving
@@ -52,6 +57,52 @@ class Pool:
     def arenas(self):
         return [(self.arena if e == self.n else None, self.slabs if e == self.n else 0)
                 for e in EDGES]
+
+
+TILES = (8, 4)
+
+
+def tile_sweep(count=512, reps=20, warmup=3, seed=60, edges=EDGES, fields=FIELDS,
+               dev="cuda:0", apply=True, log=None):
+    """Time one aggregated step (a captured graph of the whole batch) of
+    `count` random smooth sub-grids per class with each tile; returns
+    (records, {(n, F): best tile}) and sets the best tiles when `apply`."""
+    import torch
+
+    from . import hydroagg, workloads
+    recs, best = [], {}
+    stream = torch.cuda.current_stream()
+    for n in edges:
+        for nf in fields:
+            U = workloads.random_smooth(count, n=n, nfields=nf, seed=seed + 100 * n + nf)
+            u_in = torch.from_numpy(U).to(dev)
+            u_out = u_in.clone()
+            amax = torch.zeros(count, dtype=torch.float64, device=dev)
+            plan = hydroagg.Plan(hydroagg.subgrids(u_in, u_out))
+            before = hydroagg.get_tile(n, nf)
+            times = {}
+            for tile in TILES:
+                hydroagg.set_tile(n, nf, tile)
+                for _ in range(warmup):
+                    plan.graph(1e-4, 1.0 / 64, amax, stream)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    plan.graph(1e-4, 1.0 / 64, amax, stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                times[tile] = e0.elapsed_time(e1) / reps * 1e3
+                recs.append({"n": n, "nfields": nf, "tile": tile, "count": count,
+                             "us_per_step": round(times[tile], 2)})
+            plan.close()
+            best[(n, nf)] = min(times, key=lambda k: (times[k], -k))
+            hydroagg.set_tile(n, nf, best[(n, nf)] if apply else before)
+            if log:
+                log(f"tile n={n} F={nf}: " + ", ".join(f"{k}^3 {v:.1f} us" for k, v in times.items())
+                    + f" -> {best[(n, nf)]}^3")
+            del u_in, u_out, U
+    return recs, best
 
 
 def run_condition(pool, rate, widths, *, seconds=0.2, min_tasks=400, streams=2,

@@ -78,3 +78,18 @@ def test_null_batch_and_empty_batch():
     assert L.hydro_step(None, 1, 0.1, 0.1, None, None) == hydroagg.HYDRO_EINVAL
     assert L.hydro_step(None, 0, 0.1, 0.1, None, None) == hydroagg.HYDRO_OK
     assert L.hydro_step_each(None, 0, 0.1, 0.1, None, None) == hydroagg.HYDRO_OK
+
+
+def test_tile_setting_is_validated_and_round_trips():
+    L = hydroagg.lib()
+    defaults = {(n, f): hydroagg.get_tile(n, f) for n in (8, 12, 16) for f in (6, 11)}
+    assert defaults == {(8, 6): 8, (8, 11): 8, (12, 6): 4, (12, 11): 4, (16, 6): 8, (16, 11): 8}
+    for args in ((9, 11, 8), (8, 7, 8), (8, 11, 5), (8, 11, 0), (12, 6, 16)):
+        assert L.hydro_set_tile(*args) == hydroagg.HYDRO_EINVAL
+    assert L.hydro_get_tile(8, 11, None) == hydroagg.HYDRO_EINVAL
+    try:
+        hydroagg.set_tile(16, 6, 4)
+        assert hydroagg.get_tile(16, 6) == 4 and hydroagg.get_tile(16, 11) == 8
+    finally:
+        hydroagg.set_tile(16, 6, defaults[(16, 6)])
+    assert hydroagg.get_tile(16, 6) == 8

@@ -231,3 +231,52 @@ def test_layouts_mixed_in_one_batch(dev):
     assert np.array_equal(a.cpu().numpy(), ref[:12])
     assert np.array_equal(b.cpu().numpy(), interior(ref[12:], n))
     assert np.array_equal(amax.cpu().numpy(), ref_a)
+
+
+@pytest.mark.parametrize("n,nf,count", [(8, 11, 21), (8, 6, 3), (12, 11, 10), (12, 6, 4),
+                                        (16, 11, 9), (16, 6, 2)])
+def test_tiles_are_bitwise_equivalent(dev, oracle_mod, n, nf, count):
+    """8^3 and 4^3 tiles compute every face from the same cells: both match
+    the oracle, and each other far inside the parity tolerance (the two
+    kernels are compiled separately, so contractions may differ in the last
+    bits)."""
+    U = workloads.random_smooth(count, n=n, nfields=nf, seed=900 + n + nf + count)
+    levels = [s % 2 for s in range(count)]
+    before = hydroagg.get_tile(n, nf)
+    out = {}
+    try:
+        for tile in (8, 4):
+            hydroagg.set_tile(n, nf, tile)
+            print(f"tiles: n={n} F={nf} count={count} tile={tile}", flush=True)
+            out[tile] = check(U, 2e-3, 0.05, oracle_mod, levels=levels)
+    finally:
+        hydroagg.set_tile(n, nf, before)
+    diff = normwise(interior(out[4][0], n), interior(out[8][0], n))
+    da = np.max(np.abs(out[4][1] - out[8][1]) / out[8][1])
+    print(f"tile 4 vs 8: normwise {diff.max():.2e}, amax {da:.2e}", flush=True)
+    assert diff.max() <= 1e-13 and da <= 1e-14
+
+
+def test_plan_recaptures_after_a_tile_change(dev):
+    n, nf, count = 8, 11, 16
+    U = workloads.random_smooth(count, n=n, nfields=nf, seed=950)
+    u_in = torch.from_numpy(U).to(dev)
+    u_out = u_in.clone()
+    amax = torch.zeros(count, dtype=torch.float64, device=dev)
+    plan = hydroagg.Plan(hydroagg.subgrids(u_in, u_out))
+    stream = torch.cuda.current_stream()
+    before = hydroagg.get_tile(n, nf)
+    try:
+        plan.graph(1e-3, 0.05, amax, stream)
+        torch.cuda.synchronize()
+        ref = u_out.cpu().numpy().copy()
+        u_out.zero_()
+        hydroagg.set_tile(n, nf, 4 if before == 8 else 8)
+        plan.graph(1e-3, 0.05, amax, stream)
+        torch.cuda.synchronize()
+        got = u_out.cpu().numpy()
+    finally:
+        hydroagg.set_tile(n, nf, before)
+        plan.close()
+    assert normwise(interior(got, n), interior(ref, n)).max() <= 1e-13
+    assert not np.array_equal(interior(got, n), np.zeros_like(interior(got, n)))
