@@ -183,3 +183,19 @@ def test_serving_loop_admission_bound(dev):
     torch.cuda.synchronize()
     assert st["agg"]["launched"] == ntask and st["max_live"] <= 12
     assert st["slab_waits"] > 0 and np.all(lat > 0) and np.all(am > 0)
+
+
+def test_tile_sweep_chooses_and_applies(dev):
+    from paper_2210_06438_amd import tune
+    before = {(n, f): hydroagg.get_tile(n, f) for n in (8, 12, 16) for f in (6, 11)}
+    try:
+        recs, best = tune.tile_sweep(count=16, reps=2, warmup=1, dev=dev, apply=False)
+        assert set(best) == set(before) and all(t in (4, 8) for t in best.values())
+        assert len(recs) == 12 and all(r["us_per_step"] > 0 for r in recs)
+        assert {k: hydroagg.get_tile(*k) for k in before} == before      # apply=False restores
+        recs, best = tune.tile_sweep(count=16, reps=2, warmup=1, edges=(12,), fields=(11,),
+                                     dev=dev, apply=True)
+        assert hydroagg.get_tile(12, 11) == best[(12, 11)]
+    finally:
+        for (n, f), t in before.items():
+            hydroagg.set_tile(n, f, t)
