@@ -123,7 +123,7 @@ def learned_leg(args, dev):
     out = {"splits": args.learned_splits, "epochs": 2000, "features": 5,
            "overload_clip_us": learned.OVERLOAD_US,
            "exhaustive_runs_per_condition": len(learned.WIDTHS), "model_runs_per_condition": 0}
-    for name in ("timeout", "idle"):
+    for name in ("timeout", "idle_r3"):
         recs = learned.load_sweep(name)
         t0 = time.time()
         cv = learned.cross_validate(recs, splits=range(args.learned_splits), device=dev)
@@ -132,11 +132,14 @@ def learned_leg(args, dev):
                                 else "launch on width, 50 us timeout or idle stream"),
                      "model_mean_regret": round(cv["mlp_mean_regret"], 4),
                      "static_mean_regret": round(cv["static_mean_regret"], 4),
+                     "model_median_regret": round(cv["mlp_median_regret"], 4),
+                     "static_median_regret": round(cv["static_median_regret"], 4),
                      "static_widths": sorted({e["static_width"] for e in cv["splits"]}),
                      "model_wins": cv["mlp_wins"],
                      "train_seconds_per_model": round(sec / args.learned_splits, 3)}
-        log(f"learned width ({name}): model regret {cv['mlp_mean_regret']:.3f} vs best static "
-            f"{cv['static_mean_regret']:.3f}, wins {cv['mlp_wins']}/{args.learned_splits}, "
+        log(f"learned width ({name}): model regret mean {cv['mlp_mean_regret']:.3f} / median "
+            f"{cv['mlp_median_regret']:.3f} vs best static {cv['static_mean_regret']:.3f} / "
+            f"{cv['static_median_regret']:.3f}, wins {cv['mlp_wins']}/{args.learned_splits}, "
             f"{sec / args.learned_splits:.2f} s per model")
     model = learned.WidthModel(device=dev).fit(learned.load_sweep("timeout"))
     return out, model

@@ -15,6 +15,7 @@ candidate widths; the exhaustive tuner (tune.py) is its fallback and judge.
 Sweeps stored under data/ (420 records each, made by tune.py on one MI355X):
   width_sweep_timeout.json  launch on width or 50 us timeout only
   width_sweep_idle.json     also launch whenever a stream is idle
+  width_sweep_idle_r3.json  the same, median p99 of 3 arrival sequences per point
 """
 from __future__ import annotations
 
@@ -240,6 +241,8 @@ def evaluate(records, model, test_groups, static_width):
     return {"static_width": static_width, "rows": rows,
             "mlp_mean_regret": float(np.mean([r["mlp_regret"] for r in rows])),
             "static_mean_regret": float(np.mean([r["static_regret"] for r in rows])),
+            "mlp_median_regret": float(np.median([r["mlp_regret"] for r in rows])),
+            "static_median_regret": float(np.median([r["static_regret"] for r in rows])),
             "exhaustive_runs_per_condition": len(WIDTHS), "mlp_runs_per_condition": 0}
 
 
@@ -257,7 +260,10 @@ def cross_validate(records, splits=range(10), epochs=2000, lr=1e-3, model_seed=0
         ev["split"] = sp
         ev["final_loss"] = m.curve[-1]
         out.append(ev)
+    allrows = [r for e in out for r in e["rows"]]
     return {"splits": out,
             "mlp_mean_regret": float(np.mean([e["mlp_mean_regret"] for e in out])),
             "static_mean_regret": float(np.mean([e["static_mean_regret"] for e in out])),
+            "mlp_median_regret": float(np.median([r["mlp_regret"] for r in allrows])),
+            "static_median_regret": float(np.median([r["static_regret"] for r in allrows])),
             "mlp_wins": int(sum(e["mlp_mean_regret"] < e["static_mean_regret"] for e in out))}

@@ -106,29 +106,37 @@ def tile_sweep(count=512, reps=20, warmup=3, seed=60, edges=EDGES, fields=FIELDS
 
 
 def run_condition(pool, rate, widths, *, seconds=0.2, min_tasks=400, streams=2,
-                  timeout_us=50.0, seed=0, dt=1e-4, dx=1.0 / 64, flush_when_idle=False):
-    """Serve one arrival sequence at each width; returns one record per width."""
+                  timeout_us=50.0, seed=0, dt=1e-4, dx=1.0 / 64, flush_when_idle=False,
+                  repeats=1):
+    """Serve `repeats` independent arrival sequences at each width; one
+    record per width, with the median over the repeats (p99_us) and each
+    repeat's p99 (p99_runs_us)."""
     import numpy as np
 
     from . import hydroagg
     ntask = max(min_tasks, int(rate * seconds))
-    rng = np.random.Generator(np.random.PCG64([seed, pool.n, pool.nfields, int(rate)]))
-    task = rng.integers(0, pool.count, ntask).astype(np.int32)
-    arrival = np.cumsum(rng.exponential(1e6 / rate, ntask))
+    seqs = []
+    for r in range(repeats):
+        rng = np.random.Generator(np.random.PCG64([seed + 1000 * r, pool.n, pool.nfields, int(rate)]))
+        task = rng.integers(0, pool.count, ntask).astype(np.int32)
+        seqs.append((task, np.cumsum(rng.exponential(1e6 / rate, ntask))))
     out = []
     for w in widths:
-        lat, _, _, st = hydroagg.serve_run(pool.descs, task, arrival, nfields=pool.nfields, dt=dt,
-                                           dx=dx, slab_arenas=pool.arenas(), max_width=w,
-                                           timeout_us=timeout_us, n_streams=streams,
-                                           flush_when_idle=flush_when_idle)
-        span = max(st["makespan_us"], 1.0) * 1e-6
+        runs = []
+        for task, arrival in seqs:
+            lat, _, _, st = hydroagg.serve_run(pool.descs, task, arrival, nfields=pool.nfields,
+                                               dt=dt, dx=dx, slab_arenas=pool.arenas(),
+                                               max_width=w, timeout_us=timeout_us,
+                                               n_streams=streams, flush_when_idle=flush_when_idle)
+            span = max(st["makespan_us"], 1.0) * 1e-6
+            runs.append((float(np.percentile(lat, 50)), float(np.percentile(lat, 99)),
+                         float(lat.mean()), ntask / span, st["agg"]["batches"]))
+        med = [float(np.median([r[k] for r in runs])) for k in range(5)]
         out.append({"n": pool.n, "nfields": pool.nfields, "rate": rate, "width": w,
                     "streams": streams, "tasks": ntask, "flush_when_idle": bool(flush_when_idle),
-                    "p50_us": float(np.percentile(lat, 50)),
-                    "p99_us": float(np.percentile(lat, 99)),
-                    "mean_us": float(lat.mean()),
-                    "throughput": ntask / span,
-                    "batches": st["agg"]["batches"]})
+                    "p50_us": med[0], "p99_us": med[1], "mean_us": med[2], "throughput": med[3],
+                    "batches": int(med[4]), "repeats": repeats,
+                    "p99_runs_us": [round(r[1], 2) for r in runs]})
     return out
 
 
@@ -175,14 +183,17 @@ def main(argv=None):
     ap.add_argument("--streams", type=int, default=2)
     ap.add_argument("--idle-flush", action="store_true",
                     help="also launch whenever a stream is idle (off: width and timeout only)")
+    ap.add_argument("--repeats", type=int, default=1,
+                    help="independent arrival sequences per point (median p99 recorded)")
     a = ap.parse_args(argv)
     t0 = time.time()
     recs = sweep(seconds=a.seconds, streams=a.streams, flush_when_idle=a.idle_flush,
-                 log=lambda m: print(m, flush=True))
+                 repeats=a.repeats, log=lambda m: print(m, flush=True))
     with open(a.out, "w") as f:
         json.dump({"widths": WIDTHS, "edges": EDGES, "fields": FIELDS, "rates": RATES,
                    "seconds": a.seconds, "streams": a.streams, "timeout_us": 50.0,
                    "flush_when_idle": a.idle_flush, "slab_budget_mb": 64.0,
+                   "repeats": a.repeats,
                    "records": recs}, f)
     print(f"{len(recs)} records in {time.time() - t0:.0f} s -> {a.out}", flush=True)
 
