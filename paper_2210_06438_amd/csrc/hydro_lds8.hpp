@@ -26,8 +26,8 @@
 // flux, paper Section IV-B with the Kurganov-Noelle-Petrova flux) and keeps,
 // for every face, the weights w- = a+(v- - a-)/(a+ - a-) and
 // w+ = a-(a+ - v+)/(a+ - a-) of the expanded flux, with which the flux of any
-// passively advected density q is w- q(W-) + w+ q(W+).  All passive fields
-// (tau, species) are then loaded in one burst and marched from LDS.
+// passively advected density q is w- q(W-) + w+ q(W+).  The passive fields
+// (tau, species) are then loaded in two bursts and marched from LDS.
 //
 // Direction sums: lanes of the x and y waves add their flux differences into
 // a zeroed LDS accumulator with atomic adds -- exactly two adds onto zero per
@@ -357,11 +357,18 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int
     }
   }
 
-  // ---- all passive fields in one burst ----------------------------------
-  Share<NP> ps;
-  double pg[NP][6];
-  load_share<NP, MP>(uin + 5 * FS, t, ps);
-  load_ghosts<NP, MP>(uin + 5 * FS, gbase, gstride, pg);
+  // ---- passive fields: first burst -----------------------------------------
+  // The passive inputs arrive in two bursts: fields [0, NA) now, fields
+  // [NA, NP) while the first ones are marched, so the registers of the whole
+  // burst are never live together with the hydro finalize (with one burst
+  // the compiler spilled ~20 registers there; with two, none).
+  constexpr int NA = (NP + 1) / 2;
+  constexpr int NB = NP - NA;
+  constexpr int NBs = NB > 0 ? NB : 1;
+  Share<NA> ps;
+  double pg[NA][6];
+  load_share<NA, MP>(uin + 5 * FS, t, ps);
+  load_ghosts<NA, MP>(uin + 5 * FS, gbase, gstride, pg);
   __syncthreads();   // hydro sums complete; tin free
   if (dir == 2) {
 #pragma unroll
@@ -376,8 +383,15 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int
       }
     }
   }
-  store_share<NP>(tin, t, ps);
-  __syncthreads();   // tin holds every passive field; accumulator clear
+  store_share<NA>(tin, t, ps);
+  __syncthreads();   // tin holds the first passive fields; accumulator clear
+  // second burst, in flight during the first marches
+  Share<NBs> psb;
+  double pgb[NBs][6];
+  if constexpr (NB > 0) {
+    load_share<NB, MP>(uin + (5 + NA) * FS, t, psb);
+    load_ghosts<NB, MP>(uin + (5 + NA) * FS, gbase, gstride, pgb);
+  }
 
   // ---- passive fields, one at a time, from LDS ---------------------------
 #pragma unroll
@@ -388,8 +402,12 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int
     double q[1], Wm[1], Wp[1];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      q[0] = (i >= kGhost && i < kGhost + N) ? tin[p * P + lbase + (i - kGhost) * lstride]
-                                             : pg[p][i < kGhost ? i : i - N];
+      if (i >= kGhost && i < kGhost + N) {
+        q[0] = tin[p * P + lbase + (i - kGhost) * lstride];
+      } else {
+        const int gi = i < kGhost ? i : i - N;   // ghost slot 0..5
+        q[0] = p < NA ? pg[p][gi] : pgb[p - NA][gi];
+      }
       switch (i) {
         case 0: rc.step<0>(q, Wm, Wp); break;
         case 1: rc.step<1>(q, Wm, Wp); break;
@@ -410,6 +428,11 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int
         }
         Fprev = Fh;
       }
+    }
+    // the second burst goes to LDS before the barrier that ends field NA-1,
+    // so every later field finds it there
+    if constexpr (NB > 0) {
+      if (p == NA - 1) store_share<NB>(tin + NA * P, t, psb);
     }
     // Alternate two accumulator regions: field p is finished by the z lanes
     // after the barrier, while the x/y lanes may already add field p+1 into
