@@ -280,3 +280,26 @@ def test_plan_recaptures_after_a_tile_change(dev):
         plan.close()
     assert normwise(interior(got, n), interior(ref, n)).max() <= 1e-13
     assert not np.array_equal(interior(got, n), np.zeros_like(interior(got, n)))
+
+
+def test_batch_larger_than_a_staging_slot(dev, oracle_mod):
+    """66000 sub-grids (two descriptor-staging chunks of at most 65536):
+    1031 distinct ones, replicated on the device.  The distinct ones match
+    the oracle, and every copy is bitwise its original, wherever it sits."""
+    uniq = workloads.random_smooth(1031, n=8, nfields=6, seed=1200)
+    count = 66000
+    print(f"large batch: count={count} n=8 F=6", flush=True)
+    idx = torch.arange(count, device=dev) % 1031
+    u_in = torch.from_numpy(uniq).to(dev)[idx].contiguous()
+    u_out = u_in.clone()
+    amax = torch.zeros(count, dtype=torch.float64, device=dev)
+    dt, dx = 1e-3, 1.0 / 64
+    hydroagg.hydro_step(hydroagg.subgrids(u_in, u_out), dt, dx, amax)
+    torch.cuda.synchronize()
+    first = u_out[:1031]
+    assert torch.equal(u_out, first[idx]) and torch.equal(amax, amax[:1031][idx])
+    ref, ref_amax = oracle_mod.step(uniq, dt, dx)
+    got = first.cpu().numpy()
+    assert np.all(normwise(interior(got, 8), interior(ref, 8)) <= TOL)
+    assert np.max(np.abs(amax[:1031].cpu().numpy() - ref_amax) / ref_amax) <= ATOL_AMAX
+    del u_in, u_out
