@@ -120,10 +120,18 @@ class HipExec {
       d.index = i;
     }
     hipStream_t st = streams_[s];
-    HIP_OK(hipMemcpyAsync(sl.dtab, sl.htab, sizeof(DevDesc) * n, hipMemcpyHostToDevice, st));
+    // Small batches (at most kArgDescs tasks of every class) carry their
+    // descriptors in the kernel arguments: one stream operation fewer, which
+    // is most of a lightly loaded task's latency.
+    bool small = true;
+    for (int c = 0; c < hydro::api::kNumClasses; ++c) small = small && num[c] <= hydro::kArgDescs;
+    if (!small)
+      HIP_OK(hipMemcpyAsync(sl.dtab, sl.htab, sizeof(DevDesc) * n, hipMemcpyHostToDevice, st));
     for (int c = 0; c < hydro::api::kNumClasses; ++c) {
       if (!num[c]) continue;
-      int rc = hydro::api::launch_class(c, sl.dtab + off[c], num[c], dt, dx, sl.damax, st);
+      int rc = small ? hydro::api::launch_class_args(c, sl.htab + off[c], num[c], dt, dx,
+                                                     sl.damax, st)
+                     : hydro::api::launch_class(c, sl.dtab + off[c], num[c], dt, dx, sl.damax, st);
       if (rc) return rc;
     }
     HIP_OK(hipMemcpyAsync(sl.hamax, sl.damax, sizeof(double) * n, hipMemcpyDeviceToHost, st));

@@ -292,6 +292,14 @@ int launch_class(int cls, const DevDesc* table, int n, double dt, double dx, dou
                  hipStream_t s) {
   return dispatch_table(cls, table, n, dt, dx, amax, s);
 }
+
+int launch_class_args(int cls, const DevDesc* host, int n, double dt, double dx, double* amax,
+                      hipStream_t s) {
+  if (n > hydro::kArgDescs) return fail(HYDRO_EINVAL, "%d descriptors exceed the argument form", n);
+  ArgDescs a;
+  for (int i = 0; i < n; ++i) a.d[i] = host[i];
+  return dispatch_args(cls, a, n, dt, dx, amax, s);
+}
 }  // namespace api
 }  // namespace hydro
 
