@@ -61,6 +61,7 @@ class HipExec {
       HIP_OK(hipMalloc((void**)&sl.dtab, sizeof(DevDesc) * cap_));
       HIP_OK(hipMalloc((void**)&sl.damax, sizeof(double) * cap_));
       HIP_OK(hipHostMalloc((void**)&sl.hamax, sizeof(double) * cap_, hipHostMallocDefault));
+      HIP_OK(hipHostGetDevicePointer((void**)&sl.hamax_dev, sl.hamax, 0));
       HIP_OK(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
     }
     return HYDRO_OK;
@@ -123,18 +124,27 @@ class HipExec {
     // Small batches (at most kArgDescs tasks of every class) carry their
     // descriptors in the kernel arguments: one stream operation fewer, which
     // is most of a lightly loaded task's latency.
-    bool small = true;
-    for (int c = 0; c < hydro::api::kNumClasses; ++c) small = small && num[c] <= hydro::kArgDescs;
+    bool small = true, single = true;
+    for (int c = 0; c < hydro::api::kNumClasses; ++c) {
+      small = small && num[c] <= hydro::kArgDescs;
+      single = single && (num[c] == 0 || hydro::api::class_single_block(c));
+    }
+    // When every sub-grid is one work-group, each amax is a plain store and
+    // goes straight to the slot's pinned host array (device-accessible); the
+    // completion word below is written after the kernels, so the host reads
+    // it only after they finished.  Otherwise amax is combined in device
+    // memory and copied back.
+    double* amax = single ? sl.hamax_dev : sl.damax;
     if (!small)
       HIP_OK(hipMemcpyAsync(sl.dtab, sl.htab, sizeof(DevDesc) * n, hipMemcpyHostToDevice, st));
     for (int c = 0; c < hydro::api::kNumClasses; ++c) {
       if (!num[c]) continue;
-      int rc = small ? hydro::api::launch_class_args(c, sl.htab + off[c], num[c], dt, dx,
-                                                     sl.damax, st)
-                     : hydro::api::launch_class(c, sl.dtab + off[c], num[c], dt, dx, sl.damax, st);
+      int rc = small ? hydro::api::launch_class_args(c, sl.htab + off[c], num[c], dt, dx, amax, st)
+                     : hydro::api::launch_class(c, sl.dtab + off[c], num[c], dt, dx, amax, st);
       if (rc) return rc;
     }
-    HIP_OK(hipMemcpyAsync(sl.hamax, sl.damax, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    if (!single)
+      HIP_OK(hipMemcpyAsync(sl.hamax, sl.damax, sizeof(double) * n, hipMemcpyDeviceToHost, st));
     // Completion word: the stream stores the batch id into pinned host memory
     // after the amax copy, so polling completion is a memory read, not a
     // runtime call.  The event serves blocking waits.
@@ -194,6 +204,7 @@ class HipExec {
     DevDesc* dtab = nullptr;
     double* damax = nullptr;
     double* hamax = nullptr;
+    double* hamax_dev = nullptr;  // the device's address of hamax
     hipEvent_t ev = nullptr;
     bool busy = false, finished = false;
     int stream = 0, n = 0;

@@ -293,6 +293,11 @@ int launch_class(int cls, const DevDesc* table, int n, double dt, double dx, dou
   return dispatch_table(cls, table, n, dt, dx, amax, s);
 }
 
+bool class_single_block(int cls) {
+  // one work-group per sub-grid: 8^3 sub-grids with the 8^3 tile
+  return (cls == 0 || cls == 1) && g_tile[cls].load(std::memory_order_relaxed) == 8;
+}
+
 int launch_class_args(int cls, const DevDesc* host, int n, double dt, double dx, double* amax,
                       hipStream_t s) {
   if (n > hydro::kArgDescs) return fail(HYDRO_EINVAL, "%d descriptors exceed the argument form", n);

@@ -25,6 +25,10 @@ int validate_batch(const hydro_subgrid_t* sg, int32_t count, double dt, double d
 // at `table` (device memory), on stream `s`.
 int launch_class(int cls, const DevDesc* table, int n, double dt, double dx, double* amax,
                  hipStream_t s);
+// True when class `cls` steps each sub-grid with one work-group, which then
+// writes its amax slot with a plain store (no zeroing, no atomics).
+bool class_single_block(int cls);
+
 // The same with at most kArgDescs descriptors read from host memory and
 // passed in the kernel arguments (no descriptor copy on the stream).
 int launch_class_args(int cls, const DevDesc* host, int n, double dt, double dx, double* amax,
