@@ -228,7 +228,7 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-size leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--uneven-count", type=int, default=3000)
-    ap.add_argument("--uneven-steps", type=int, default=20)
+    ap.add_argument("--uneven-steps", type=int, default=100)
     ap.add_argument("--uneven-each", type=int, default=1,
                     help="1: also time the uneven batch with one launch per sub-grid")
     ap.add_argument("--serve-rates", type=float, nargs="*", default=[20000.0, 200000.0, 2000000.0])

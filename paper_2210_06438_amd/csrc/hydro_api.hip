@@ -322,6 +322,14 @@ struct hydro_plan {
   double g_dt = -1.0, g_dx = -1.0;
   double* g_amax = nullptr;
   uint64_t g_tiles = ~0ull;  // tile epoch of the captured graph
+  // Branches of the captured graph: every class after the first is captured
+  // on a side stream forked from the capture stream (fork event) and joined
+  // back (its own event), so the classes are independent graph nodes that
+  // run concurrently and the partly filled last wave of one class's
+  // work-groups overlaps the work of the others.
+  hipStream_t side[kClasses] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kClasses] = {};
 };
 
 namespace {
@@ -333,6 +341,50 @@ int plan_launches(hydro_plan* p, double dt, double dx, double* amax, hipStream_t
     if (rc) return rc;
   }
   return HYDRO_OK;
+}
+
+// Record one step into the graph being captured on p->capture, one branch
+// per class.  Never returns early: a failed call still leaves every side
+// stream joined, so the caller can always end the capture.
+int plan_capture_branches(hydro_plan* p, double dt, double dx, double* amax) {
+  int rc = HYDRO_OK;
+  auto hip = [&rc](hipError_t e, const char* what) {
+    if (e != hipSuccess && rc == HYDRO_OK)
+      rc = fail(HYDRO_EHIP, "%s failed: %s", what, hipGetErrorString(e));
+    return e == hipSuccess;
+  };
+  const bool forked = hip(hipEventRecord(p->fork, p->capture), "hipEventRecord(fork)");
+  bool first = true;
+  for (int c = 0; c < kClasses; ++c) {
+    if (!p->num[c]) continue;
+    if (first) {
+      first = false;
+      if (rc == HYDRO_OK) rc = dispatch_table(c, p->table + p->off[c], p->num[c], dt, dx, amax, p->capture);
+      continue;
+    }
+    if (!forked || !hip(hipStreamWaitEvent(p->side[c], p->fork, 0), "hipStreamWaitEvent(fork)"))
+      continue;
+    if (rc == HYDRO_OK) {
+      int r = dispatch_table(c, p->table + p->off[c], p->num[c], dt, dx, amax, p->side[c]);
+      if (r) rc = r;
+    }
+    if (hip(hipEventRecord(p->join[c], p->side[c]), "hipEventRecord(join)"))
+      hip(hipStreamWaitEvent(p->capture, p->join[c], 0), "hipStreamWaitEvent(join)");
+  }
+  return rc;
+}
+
+void plan_free(hydro_plan* p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->table) (void)hipFree(p->table);
+  for (int c = 0; c < kClasses; ++c) {
+    if (p->join[c]) (void)hipEventDestroy(p->join[c]);
+    if (p->side[c]) (void)hipStreamDestroy(p->side[c]);
+  }
+  if (p->fork) (void)hipEventDestroy(p->fork);
+  if (p->capture) (void)hipStreamDestroy(p->capture);
+  delete p;
 }
 
 }  // namespace
@@ -394,22 +446,34 @@ int hydro_plan_create(hydro_plan_t** out, const hydro_subgrid_t* sg, int32_t cou
   memcpy(fill, p->off, sizeof fill);
   for (int i = 0; i < count; ++i) host[fill[class_of(sg[i].n, sg[i].nfields)]++] = to_dev(sg[i], i);
   {
+    // capture stream, and a side stream + join event for every class present
+    // after the first (see plan_capture_branches)
     hipError_t e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+    bool first = true;
+    for (int c = 0; c < kClasses && e == hipSuccess; ++c) {
+      if (!p->num[c]) continue;
+      if (first) {
+        first = false;
+        continue;
+      }
+      e = hipStreamCreateWithFlags(&p->side[c], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join[c], hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
-      delete p;
-      return fail(HYDRO_EHIP, "hipStreamCreate(plan): %s", hipGetErrorString(e));
+      plan_free(p);
+      return fail(HYDRO_EHIP, "plan streams/events: %s", hipGetErrorString(e));
     }
   }
   if (count > 0) {
     hipError_t e = hipMalloc((void**)&p->table, sizeof(DevDesc) * count);
     if (e != hipSuccess) {
-      delete p;
+      plan_free(p);
       return fail(HYDRO_EHIP, "hipMalloc(plan table): %s", hipGetErrorString(e));
     }
     e = hipMemcpy(p->table, host.data(), sizeof(DevDesc) * count, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-      (void)hipFree(p->table);
-      delete p;
+      plan_free(p);
       return fail(HYDRO_EHIP, "hipMemcpy(plan table): %s", hipGetErrorString(e));
     }
   }
@@ -443,7 +507,7 @@ int hydro_plan_launch_graph(hydro_plan_t* p, double dt, double dx, double* amax_
       p->graph = nullptr;
     }
     HIP_TRY(hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal));
-    rc = plan_launches(p, dt, dx, amax_dev, p->capture);
+    rc = plan_capture_branches(p, dt, dx, amax_dev);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(p->capture, &g);
     if (rc) {
@@ -467,11 +531,7 @@ int hydro_plan_destroy(hydro_plan_t* p) {
   if (!p) return HYDRO_OK;
   int rc = HYDRO_OK;
   if (hipDeviceSynchronize() != hipSuccess) rc = fail(HYDRO_EHIP, "hipDeviceSynchronize failed");
-  if (p->exec) (void)hipGraphExecDestroy(p->exec);
-  if (p->graph) (void)hipGraphDestroy(p->graph);
-  if (p->table) (void)hipFree(p->table);
-  if (p->capture) (void)hipStreamDestroy(p->capture);
-  delete p;
+  plan_free(p);
   return rc;
 }
 

@@ -303,3 +303,38 @@ def test_batch_larger_than_a_staging_slot(dev, oracle_mod):
     assert np.all(normwise(interior(got, 8), interior(ref, 8)) <= TOL)
     assert np.max(np.abs(amax[:1031].cpu().numpy() - ref_amax) / ref_amax) <= ATOL_AMAX
     del u_in, u_out
+
+
+def test_plan_graph_branches_match_eager_step(dev):
+    """A plan over all six (n, F) classes: its graph holds one branch per
+    class, and every replay (with eager work between them) is bitwise the
+    eager hydro_step result, outputs and amax."""
+    parts = []
+    for k, (n, nf) in enumerate([(8, 6), (8, 11), (12, 6), (12, 11), (16, 6), (16, 11)]):
+        U = workloads.random_smooth(20, n=n, nfields=nf, seed=1300 + k)
+        u_in = torch.from_numpy(U).to(dev)
+        parts.append((u_in, u_in.clone(), u_in.clone()))
+    count = 20 * len(parts)
+    graph_descs = hydroagg.concat(*[hydroagg.subgrids(a, b) for a, b, _ in parts])
+    eager_descs = hydroagg.concat(*[hydroagg.subgrids(a, c) for a, _, c in parts])
+    amax_g = torch.zeros(count, dtype=torch.float64, device=dev)
+    amax_e = torch.zeros(count, dtype=torch.float64, device=dev)
+    dt, dx = 2e-3, 0.05
+    print("plan branches: 6 classes x 20 sub-grids", flush=True)
+    hydroagg.hydro_step(eager_descs, dt, dx, amax_e)
+    torch.cuda.synchronize()
+    plan = hydroagg.Plan(graph_descs)
+    stream = torch.cuda.current_stream()
+    try:
+        for replay in range(3):
+            for _, b, _ in parts:
+                b.fill_(-1.0)
+            amax_g.zero_()
+            plan.graph(dt, dx, amax_g, stream)
+            torch.cuda.synchronize()
+            for _, b, c in parts:
+                i = (slice(None), slice(None), slice(3, -3), slice(3, -3), slice(3, -3))
+                assert torch.equal(b[i], c[i]), f"replay {replay}"
+            assert torch.equal(amax_g, amax_e), f"replay {replay}"
+    finally:
+        plan.close()
