@@ -63,10 +63,12 @@ TILES = (8, 4)
 
 
 def tile_sweep(count=512, reps=20, warmup=3, seed=60, edges=EDGES, fields=FIELDS,
-               dev="cuda:0", apply=True, log=None):
+               dev="cuda:0", apply=True, log=None, rounds=3):
     """Time one aggregated step (a captured graph of the whole batch) of
     `count` random smooth sub-grids per class with each tile; returns
-    (records, {(n, F): best tile}) and sets the best tiles when `apply`."""
+    (records, {(n, F): best tile}) and sets the best tiles when `apply`.
+    The tiles are timed in turn for `rounds` rounds and each keeps its median
+    round, so a clock still rising at the start favours neither."""
     import torch
 
     from . import hydroagg, workloads
@@ -80,21 +82,25 @@ def tile_sweep(count=512, reps=20, warmup=3, seed=60, edges=EDGES, fields=FIELDS
             amax = torch.zeros(count, dtype=torch.float64, device=dev)
             plan = hydroagg.Plan(hydroagg.subgrids(u_in, u_out))
             before = hydroagg.get_tile(n, nf)
-            times = {}
+            runs = {tile: [] for tile in TILES}
+            for _ in range(rounds):
+                for tile in TILES:
+                    hydroagg.set_tile(n, nf, tile)
+                    for _ in range(warmup):
+                        plan.graph(1e-4, 1.0 / 64, amax, stream)
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(reps):
+                        plan.graph(1e-4, 1.0 / 64, amax, stream)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    runs[tile].append(e0.elapsed_time(e1) / reps * 1e3)
+            times = {tile: sorted(r)[len(r) // 2] for tile, r in runs.items()}
             for tile in TILES:
-                hydroagg.set_tile(n, nf, tile)
-                for _ in range(warmup):
-                    plan.graph(1e-4, 1.0 / 64, amax, stream)
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                for _ in range(reps):
-                    plan.graph(1e-4, 1.0 / 64, amax, stream)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                times[tile] = e0.elapsed_time(e1) / reps * 1e3
                 recs.append({"n": n, "nfields": nf, "tile": tile, "count": count,
-                             "us_per_step": round(times[tile], 2)})
+                             "us_per_step": round(times[tile], 2),
+                             "rounds_us": [round(x, 2) for x in runs[tile]]})
             plan.close()
             best[(n, nf)] = min(times, key=lambda k: (times[k], -k))
             hydroagg.set_tile(n, nf, best[(n, nf)] if apply else before)
