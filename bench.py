@@ -43,16 +43,27 @@ def bytes_per_subgrid(n, nf):
     return floor, tile
 
 
-def measured_traffic(version, workload, kernel):
+def kernels_hash(version):
+    """The "kernels <hash>" part of hydro_version(), or None."""
+    parts = version.split()
+    return parts[parts.index("kernels") + 1] if "kernels" in parts[:-1] else None
+
+
+def measured_traffic(version, workload, kernel, path=None):
     """HBM bytes per launch from the committed rocprofv3 counter record, or
-    None when that record was taken on another build or another kernel."""
-    path = os.path.join(ROOT, "paper_2210_06438_amd", "measured_traffic.json")
+    None when that record was taken on other kernels (their sources or
+    flags differ), another workload or another kernel."""
+    if path is None:
+        path = os.path.join(ROOT, "paper_2210_06438_amd", "measured_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_version") != version or rec.get("workload") != workload:
+    here = kernels_hash(version)
+    if here is None or kernels_hash(rec.get("kernel_version", "")) != here:
+        return None
+    if rec.get("workload") != workload:
         return None
     if kernel.split("<")[0] not in rec.get("kernel", ""):
         return None

@@ -254,7 +254,9 @@ int hydro_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t
 /* Thread-local text of the last error on the calling thread ("" if none). */
 const char *hydro_last_error(void);
 
-/* Library build string (kernel variant, target). */
+/* Library build string: target, a hash of every library source ("src X")
+ * and a hash of the hydro kernels' sources and compile flags ("kernels Y"),
+ * which changes only when their machine code can.  Static storage. */
 const char *hydro_version(void);
 
 #ifdef __cplusplus

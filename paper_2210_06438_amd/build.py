@@ -39,12 +39,30 @@ def source_hash() -> str:
     return h.hexdigest()[:12]
 
 
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f)
+                  for f in ("hydro_kernel.hpp", "hydro_lds8.hpp", "hydro_q4.hpp")]
+
+
+def kernel_hash() -> str:
+    """Short hash of what fixes the hydro kernels' machine code: their
+    sources (device code and launch geometry) and the compile flags.  Host
+    code around them can change without changing it, so a kernel measurement
+    (profiler counters) stays tied to the kernels it was taken on."""
+    h = hashlib.sha1(" ".join(FLAGS).encode())
+    for f in KERNEL_SOURCES:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
 def build(verbose: bool = False) -> str:
     for d in SOURCES:
         if not os.path.exists(d):
             raise FileNotFoundError(d)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, f'-DHYDRO_SRC_HASH="{source_hash()}"', *SOURCES, "-o", tmp]
+    cmd = [HIPCC, *FLAGS, f'-DHYDRO_SRC_HASH="{source_hash()}"',
+           f'-DHYDRO_KERNEL_HASH="{kernel_hash()}"', *SOURCES, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -141,30 +141,23 @@ int validate(const hydro_subgrid_t* sg, int32_t count, double dt, double dx) {
 std::atomic<int> g_tile[kClasses] = {{8}, {8}, {4}, {4}, {8}, {8}};
 std::atomic<uint64_t> g_tile_epoch{0};
 
-// Work-groups per sub-grid of edge N with tile T.
-template <int N>
-int groups_per_subgrid(int tile) {
-  return tile == 4 ? hydro::Q4Grid<N + 6>::kGroups : hydro::Blocks<N + 6>::kPerSubgrid;
-}
-
-int grid_for(int n, int B) { return B == 1 ? n : ((n + 7) / 8) * 8 * B; }
 
 template <int N, int F>
 int launch_table(const DevDesc* table, int n, double dt, double dx, double* amax,
                  hipStream_t stream) {
   if (n <= 0) return HYDRO_OK;
   const int tile = g_tile[class_of(N, F)].load(std::memory_order_relaxed);
-  const int B = groups_per_subgrid<N>(tile);
+  const int B = hydro::groups_per_subgrid<N + 6>(tile);
   if (B > 1 && amax) {
     hipLaunchKernelGGL(hydro::amax_zero_table, dim3((n + 255) / 256), dim3(256), 0, stream,
                        table, n, amax);
     HIP_TRY(hipGetLastError());
   }
   if (tile == 4)
-    hipLaunchKernelGGL((hydro::hydro_q4_kernel<F, N + 6>), dim3(grid_for(n, B)),
+    hipLaunchKernelGGL((hydro::hydro_q4_kernel<F, N + 6>), dim3(hydro::grid_for(n, B)),
                        dim3(hydro::Q4::kThreads), 0, stream, table, n, dt, dx, amax);
   else
-    hipLaunchKernelGGL((hydro::hydro_lds8_kernel<F, N + 6>), dim3(grid_for(n, B)),
+    hipLaunchKernelGGL((hydro::hydro_lds8_kernel<F, N + 6>), dim3(hydro::grid_for(n, B)),
                        dim3(hydro::Lds8::kThreads), 0, stream, table, n, dt, dx, amax);
   HIP_TRY(hipGetLastError());
   return HYDRO_OK;
@@ -175,7 +168,7 @@ int launch_args(const ArgDescs& a, int n, double dt, double dx, double* amax,
                 hipStream_t stream) {
   if (n <= 0) return HYDRO_OK;
   const int tile = g_tile[class_of(N, F)].load(std::memory_order_relaxed);
-  const int B = groups_per_subgrid<N>(tile);
+  const int B = hydro::groups_per_subgrid<N + 6>(tile);
   if (B > 1 && amax) {
     hipLaunchKernelGGL(hydro::amax_zero_args, dim3(1), dim3(64), 0, stream, a, n, amax);
     HIP_TRY(hipGetLastError());
@@ -540,6 +533,9 @@ const char* hydro_last_error(void) { return g_err; }
 #ifndef HYDRO_SRC_HASH
 #define HYDRO_SRC_HASH "unknown"
 #endif
+#ifndef HYDRO_KERNEL_HASH
+#define HYDRO_KERNEL_HASH "unknown"
+#endif
 int hydro_set_tile(int32_t n, int32_t nfields, int32_t tile) {
   hydro::api::clear_error();
   const int c = class_of(n, nfields);
@@ -559,6 +555,8 @@ int hydro_get_tile(int32_t n, int32_t nfields, int32_t* tile) {
   return HYDRO_OK;
 }
 
-const char* hydro_version(void) { return "hydroagg gfx950 src " HYDRO_SRC_HASH; }
+const char* hydro_version(void) {
+  return "hydroagg gfx950 src " HYDRO_SRC_HASH " kernels " HYDRO_KERNEL_HASH;
+}
 
 }  // extern "C"

@@ -316,4 +316,15 @@ __global__ void __launch_bounds__(Q4::kThreads, 2)
   q4_step<F, MP>(d, blockIdx.x % B, dt, dx, amax_out);
 }
 
+// Launch geometry shared by every table launch.  Work-groups per sub-grid
+// of parent edge MP with tile 4 or 8; a table launch over `count` sub-grids
+// of B work-groups each rounds the count up to whole multiples of 8 so the
+// work-groups of one sub-grid get indices equal modulo 8 (one XCD).
+template <int MP>
+inline int groups_per_subgrid(int tile) {
+  return tile == 4 ? Q4Grid<MP>::kGroups : Blocks<MP>::kPerSubgrid;
+}
+
+inline int grid_for(int count, int B) { return B == 1 ? count : ((count + 7) / 8) * 8 * B; }
+
 }  // namespace hydro

@@ -1,0 +1,43 @@
+"""Host logic of bench.py: the committed counter record is used only for the
+kernels it was taken on."""
+import json
+
+import bench
+
+V = "hydroagg gfx950 src aaaaaaaaaaaa kernels 111111111111"
+K = "void hydro::hydro_lds8_kernel<11, 14>(hydro::DevDesc const*, int, double, double, double*)"
+
+
+def write(tmp_path, version, workload="4096x8^3 F=11", kernel=K):
+    p = tmp_path / "rec.json"
+    p.write_text(json.dumps({"kernel_version": version, "kernel": kernel, "workload": workload,
+                             "traffic_bytes_per_launch": 1129123938.3}))
+    return str(p)
+
+
+def test_kernels_hash_parsing():
+    assert bench.kernels_hash(V) == "111111111111"
+    assert bench.kernels_hash("hydroagg gfx950 src aaaaaaaaaaaa") is None
+    assert bench.kernels_hash("") is None
+    assert bench.kernels_hash("x kernels") is None
+
+
+def test_record_follows_the_kernels_not_the_host_code(tmp_path):
+    p = write(tmp_path, V)
+    other_host = "hydroagg gfx950 src bbbbbbbbbbbb kernels 111111111111"
+    assert bench.measured_traffic(other_host, "4096x8^3 F=11", "hydro_lds8_kernel<11,14>", p) == 1129123938
+    other_kernels = "hydroagg gfx950 src aaaaaaaaaaaa kernels 222222222222"
+    assert bench.measured_traffic(other_kernels, "4096x8^3 F=11", "hydro_lds8_kernel<11,14>", p) is None
+
+
+def test_record_needs_same_workload_and_kernel(tmp_path):
+    p = write(tmp_path, V)
+    assert bench.measured_traffic(V, "2048x8^3 F=11", "hydro_lds8_kernel<11,14>", p) is None
+    assert bench.measured_traffic(V, "4096x8^3 F=11", "hydro_q4_kernel<11,14>", p) is None
+
+
+def test_old_records_without_a_kernels_hash_are_not_used(tmp_path):
+    p = write(tmp_path, "hydroagg gfx950 src aaaaaaaaaaaa")
+    assert bench.measured_traffic(V, "4096x8^3 F=11", "hydro_lds8_kernel<11,14>", p) is None
+    missing = str(tmp_path / "missing.json")
+    assert bench.measured_traffic(V, "4096x8^3 F=11", "hydro_lds8_kernel<11,14>", missing) is None
