@@ -46,7 +46,112 @@ def counter(d, match, name, grid=None):
     return vals
 
 
+def calibration(fetch_dir, write_dir, copy_bytes):
+    """Bytes per counted byte of FETCH_SIZE and WRITE_SIZE, from the plain
+    device copy of known size in the same run."""
+    f_c = max(counter(fetch_dir, "copyBuffer", "FETCH_SIZE"))
+    w_c = max(counter(write_dir, "copyBuffer", "WRITE_SIZE"))
+    return copy_bytes / (f_c * 1024.0), copy_bytes / (w_c * 1024.0)
+
+
+def step_spans(kt_dir, parts, skip=0):
+    """Wall span of every step of a multi-class launch whose class kernels
+    run concurrently: the traced dispatches of the `parts` ((match, grid)
+    pairs), in start order, cut into groups holding one dispatch of each
+    part; span = last end - first start of a complete group.  The first
+    `skip` complete groups are left out."""
+    ev = []
+    for r in _rows(kt_dir, "run_kernel_trace.csv"):
+        for k, (match, grid) in enumerate(parts):
+            if match in r["Kernel_Name"] and int(r["Grid_Size_X"]) == grid:
+                ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), k))
+    ev.sort()
+    spans, group = [], {}
+    for st, en, k in ev:
+        if k in group:
+            group = {}
+        group[k] = (st, en)
+        if len(group) == len(parts):
+            spans.append(max(e for _, e in group.values()) - min(s_ for s_, _ in group.values()))
+            group = {}
+    spans = spans[skip:]
+    if not spans:
+        raise SystemExit("no complete step in the kernel trace")
+    return spans
+
+
+def main_step(argv):
+    """Summary of one multi-class step: per class the counters and the
+    kernel durations (which overlap), and the step's wall span."""
+    ap = argparse.ArgumentParser(prog="profile_summary.py step")
+    ap.add_argument("--kt", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--part", action="append", required=True,
+                    help="MATCH|GRID|LAUNCH_BYTES|LABEL for one class kernel")
+    ap.add_argument("--copy-bytes", type=float, required=True)
+    ap.add_argument("--version", required=True)
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--command", required=True)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--skip", type=int, default=0,
+                    help="leading steps left out of the span (e.g. an eager pass)")
+    a = ap.parse_args(argv)
+    f_scale, w_scale = calibration(a.fetch, a.write, a.copy_bytes)
+    parts = [p.split("|") for p in a.part]
+    rows, tot_alg, tot_traffic = [], 0.0, 0.0
+    for match, grid, lb, label in parts:
+        grid, lb = int(grid), float(lb)
+        ks = kernel_stats(a.kt, match, grid)
+        rd = statistics.median(counter(a.fetch, match, "FETCH_SIZE", grid)) * 1024.0 * f_scale
+        wr = statistics.median(counter(a.write, match, "WRITE_SIZE", grid)) * 1024.0 * w_scale
+        tot_alg += lb
+        tot_traffic += rd + wr
+        rows.append(f"| {label} | `{ks['name'].split('(')[0].replace('void ', '')}` | {grid} | "
+                    f"{ks['avg_ns'] / 1e3:.1f} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | "
+                    f"{lb / 1e6:.1f} | {(rd + wr) / lb:.3f} |")
+    spans = step_spans(a.kt, [(m, int(g)) for m, g, _, _ in parts], a.skip)
+    avg = statistics.mean(spans) * 1e-9
+    lines = [
+        "# Multi-class step: class kernels as concurrent graph branches",
+        "",
+        f"- workload: {a.workload}",
+        f"- library: `{a.version}`",
+        f"- command: `{a.command}`",
+        f"- counters: the same command with `--pmc FETCH_SIZE` and `--pmc WRITE_SIZE`"
+        " (one counter per run; counter runs serialise the dispatches)",
+        f"- copy calibration (bytes per counted byte): read x{f_scale:.4f}, write x{w_scale:.4f}",
+        "",
+        "Per class (durations overlap: the classes run side by side):",
+        "",
+        "| class | kernel | grid | avg duration us | HBM read MB | HBM write MB | "
+        "algorithmic MB | traffic / algorithmic |",
+        "|---|---|---|---|---|---|---|---|",
+        *rows,
+        "",
+        "Whole step (first start to last end of one dispatch of every class):",
+        "",
+        "| quantity | value |",
+        "|---|---|",
+        f"| steps | {len(spans)}" + (f" (the first {a.skip} left out)" if a.skip else "") + " |",
+        f"| step span | {avg * 1e6:.1f} us (median {statistics.median(spans) / 1e3:.1f}, "
+        f"min {min(spans) / 1e3:.1f}, max {max(spans) / 1e3:.1f}) |",
+        f"| HBM traffic per step | {tot_traffic / 1e6:.1f} MB |",
+        f"| algorithmic bytes per step | {tot_alg / 1e6:.1f} MB |",
+        f"| traffic / algorithmic | {tot_traffic / tot_alg:.3f} |",
+        f"| algorithmic GB/s at average span | {tot_alg / avg / 1e9:.0f} |",
+        "",
+    ]
+    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main():
+    import sys
+    if len(sys.argv) > 1 and sys.argv[1] == "step":
+        return main_step(sys.argv[2:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--kt", required=True)
     ap.add_argument("--fetch", required=True)
@@ -68,10 +173,7 @@ def main():
     ks = kernel_stats(a.kt, a.kernel, a.grid)
     f_h = statistics.median(counter(a.fetch, a.kernel, "FETCH_SIZE", a.grid))
     w_h = statistics.median(counter(a.write, a.kernel, "WRITE_SIZE", a.grid))
-    f_c = max(counter(a.fetch, "copyBuffer", "FETCH_SIZE"))
-    w_c = max(counter(a.write, "copyBuffer", "WRITE_SIZE"))
-    f_scale = a.copy_bytes / (f_c * 1024.0)
-    w_scale = a.copy_bytes / (w_c * 1024.0)
+    f_scale, w_scale = calibration(a.fetch, a.write, a.copy_bytes)
     rd = f_h * 1024.0 * f_scale
     wr = w_h * 1024.0 * w_scale
     traffic = rd + wr
