@@ -25,6 +25,7 @@ if ROOT not in sys.path:
 
 METRIC = "FP64 hydro cell-updates/s aggregated vs per-subgrid launch; %HBM roofline; p99 latency"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 GHOST = 3
 
 
@@ -49,12 +50,12 @@ def kernels_hash(version):
     return parts[parts.index("kernels") + 1] if "kernels" in parts[:-1] else None
 
 
-def measured_traffic(version, workload, kernel, path=None):
-    """HBM bytes per launch from the committed rocprofv3 counter record, or
-    None when that record was taken on other kernels (their sources or
-    flags differ), another workload or another kernel."""
+def counter_record(name, version, workload, kernel, path=None):
+    """A committed rocprofv3 counter record (paper_2210_06438_amd/<name>),
+    or None when it was taken on other kernels (their sources or flags
+    differ), another workload or another kernel."""
     if path is None:
-        path = os.path.join(ROOT, "paper_2210_06438_amd", "measured_traffic.json")
+        path = os.path.join(ROOT, "paper_2210_06438_amd", name)
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -67,7 +68,26 @@ def measured_traffic(version, workload, kernel, path=None):
         return None
     if kernel.split("<")[0] not in rec.get("kernel", ""):
         return None
-    return int(rec["traffic_bytes_per_launch"])
+    return rec
+
+
+def measured_traffic(version, workload, kernel, path=None):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    rec = counter_record("measured_traffic.json", version, workload, kernel, path)
+    return None if rec is None else int(rec["traffic_bytes_per_launch"])
+
+
+def measured_fp64(version, workload, kernel, kernel_ms, path=None):
+    """FP64 operations per launch (SQ_INSTS_VALU_*_F64) and the rate they
+    give at the kernel duration measured in this run."""
+    rec = counter_record("measured_fp64.json", version, workload, kernel, path)
+    if rec is None:
+        return None
+    flop = float(rec["fp64_flop_per_launch"])
+    tflops = flop / (kernel_ms * 1e-3) / 1e12
+    return {"flop_per_launch": int(flop), "achieved_tflops": round(tflops, 2),
+            "peak_tflops": FP64_PEAK_TFLOPS, "frac": round(tflops / FP64_PEAK_TFLOPS, 4),
+            "valu_insts_per_wave": round(float(rec["valu_insts_per_wave"]), 1)}
 
 
 def uneven_leg(args, torch, hydroagg, workloads, dev, stream):
@@ -403,6 +423,7 @@ def main():
                   "around each of --steps launches on the launch stream",
         "floor_bytes_per_launch": floor_b * count,
         "measured_copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
+        "fp64": measured_fp64(version, workload_name, kname, kernel_ms),
     }
 
     cpu = None

@@ -148,10 +148,95 @@ def main_step(argv):
     print("\n".join(lines))
 
 
+PASS1 = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64",
+         "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_LDS", "SQ_INSTS_SALU"]
+PASS2 = ["SQ_WAVES", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_ACTIVE_INST_VALU",
+         "SQ_ACTIVE_INST_LDS", "SQ_WAIT_INST_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_INST_ANY"]
+
+
+def main_sq(argv):
+    """FP64 operation count and instruction mix of one kernel from two SQ
+    counter runs, with the kernel's average duration from a kernel-trace run.
+    SQ_INSTS_VALU_*_F64 count wave instructions; every lane of this kernel's
+    arithmetic is active, so FLOP = 64 x (ADD + MUL + TRANS + 2 FMA).  FP64
+    min/max/compare instructions are not floating-point operations and are
+    not counted."""
+    ap = argparse.ArgumentParser(prog="profile_summary.py sq")
+    ap.add_argument("--kt", required=True)
+    ap.add_argument("--sq1", required=True)
+    ap.add_argument("--sq2", required=True)
+    ap.add_argument("--kernel", required=True)
+    ap.add_argument("--grid", type=int, required=True)
+    ap.add_argument("--cells", type=float, required=True, help="cell updates per launch")
+    ap.add_argument("--version", required=True)
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--command", required=True,
+                    help="the profiled program (what follows -- in both counter passes)")
+    ap.add_argument("--kt-command", required=True, help="the kernel-trace command")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--json", default=None)
+    a = ap.parse_args(argv)
+
+    def c(d, name):
+        return statistics.median(counter(d, a.kernel, name, a.grid))
+    waves = c(a.sq1, "SQ_WAVES")
+    add, mul, fma, trans = (c(a.sq1, f"SQ_INSTS_VALU_{k}_F64") for k in ("ADD", "MUL", "FMA", "TRANS"))
+    valu, lds, salu = c(a.sq1, "SQ_INSTS_VALU"), c(a.sq1, "SQ_INSTS_LDS"), c(a.sq1, "SQ_INSTS_SALU")
+    wave_q = c(a.sq2, "SQ_WAVE_CYCLES")
+    valu_q = c(a.sq2, "SQ_ACTIVE_INST_VALU")
+    lds_q, conf_q = c(a.sq2, "SQ_ACTIVE_INST_LDS"), c(a.sq2, "SQ_LDS_BANK_CONFLICT")
+    ks = kernel_stats(a.kt, a.kernel, a.grid)
+    flop = 64.0 * (add + mul + trans + 2.0 * fma)
+    avg_s = ks["avg_ns"] * 1e-9
+    tflops = flop / avg_s / 1e12
+    lines = [
+        f"# {ks['name']}: FP64 operations and instruction mix",
+        "",
+        f"- workload: {a.workload}",
+        f"- library: `{a.version}`",
+        f"- pass 1: `rocprofv3 --pmc {' '.join(PASS1)} --output-format csv -d gpurun_out/sq1 "
+        f"-o run -- {a.command}`",
+        f"- pass 2: `rocprofv3 --pmc {' '.join(PASS2)} --output-format csv -d gpurun_out/sq2 "
+        f"-o run -- {a.command}`",
+        f"- duration: `{a.kt_command}`",
+        "- FLOP = 64 x (ADD + MUL + TRANS + 2 FMA) wave instructions (all lanes active); "
+        "FP64 min/max/compare not counted",
+        "",
+        "| quantity | value |",
+        "|---|---|",
+        f"| waves per launch | {waves:.0f} |",
+        f"| VALU instructions per wave | {valu / waves:.0f} |",
+        f"| FP64 ADD / MUL / FMA / TRANS per wave | {add / waves:.0f} / {mul / waves:.0f} / "
+        f"{fma / waves:.0f} / {trans / waves:.0f} |",
+        f"| LDS / SALU instructions per wave | {lds / waves:.0f} / {salu / waves:.0f} |",
+        f"| FP64 FLOP per launch | {flop / 1e9:.3f} G |",
+        f"| FP64 FLOP per cell update | {flop / a.cells:.0f} |",
+        f"| kernel average duration (trace) | {ks['avg_ns'] / 1e3:.1f} us |",
+        f"| achieved FP64 rate | {tflops:.2f} TFLOP/s ({tflops / 78.6:.1%} of 78.6) |",
+        f"| wave life (SQ_WAVE_CYCLES, read as 4-cycle units) | {wave_q / waves * 4 / 2.4e3:.1f} us at 2.4 GHz |",
+        f"| VALU busy per wave (SQ_ACTIVE_INST_VALU) | {valu_q / waves * 4 / 2.4e3:.1f} us "
+        f"({valu_q / wave_q:.0%} of its life) |",
+        f"| LDS active / bank-conflict cycles per wave | {lds_q / waves * 4:.0f} / {conf_q / waves * 4:.0f} |",
+        "",
+    ]
+    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+    if a.json:
+        with open(a.json, "w") as f:
+            json.dump({"kernel_version": a.version, "kernel": ks["name"], "workload": a.workload,
+                       "fp64_flop_per_launch": flop, "valu_insts_per_wave": valu / waves,
+                       "waves_per_launch": waves}, f, indent=1)
+            f.write("\n")
+
+
 def main():
     import sys
     if len(sys.argv) > 1 and sys.argv[1] == "step":
         return main_step(sys.argv[2:])
+    if len(sys.argv) > 1 and sys.argv[1] == "sq":
+        return main_sq(sys.argv[2:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--kt", required=True)
     ap.add_argument("--fetch", required=True)

@@ -41,3 +41,14 @@ def test_old_records_without_a_kernels_hash_are_not_used(tmp_path):
     assert bench.measured_traffic(V, "4096x8^3 F=11", "hydro_lds8_kernel<11,14>", p) is None
     missing = str(tmp_path / "missing.json")
     assert bench.measured_traffic(V, "4096x8^3 F=11", "hydro_lds8_kernel<11,14>", missing) is None
+
+
+def test_fp64_rate_from_the_record(tmp_path):
+    p = tmp_path / "fp64.json"
+    p.write_text(json.dumps({"kernel_version": V, "kernel": K, "workload": "4096x8^3 F=11",
+                             "fp64_flop_per_launch": 3.0e9, "valu_insts_per_wave": 5000.0}))
+    r = bench.measured_fp64(V, "4096x8^3 F=11", "hydro_lds8_kernel<11,14>", 0.3, str(p))
+    assert r["flop_per_launch"] == 3000000000 and r["achieved_tflops"] == 10.0
+    assert r["frac"] == round(10.0 / 78.6, 4)
+    other = "hydroagg gfx950 src aaaaaaaaaaaa kernels 999999999999"
+    assert bench.measured_fp64(other, "4096x8^3 F=11", "hydro_lds8_kernel<11,14>", 0.3, str(p)) is None
