@@ -124,9 +124,10 @@ int hydro_step_each(const hydro_subgrid_t *sg, int32_t count, double dt,
  * the step path).  hydro_plan_step then only launches kernels: one per
  * (n, nfields) class, with the results and errors of hydro_step.
  * hydro_plan_launch_graph runs the same launches as ONE hipGraph launch on
- * `stream`, with one independent branch per class, so the classes of a
- * mixed batch run concurrently (results are those of hydro_plan_step, bit
- * for bit); the graph is captured on private streams at first use and
+ * `stream`; classes of at least 1024 work-groups become independent
+ * branches of the graph and run concurrently, smaller ones run in sequence
+ * (results are those of hydro_plan_step, bit for bit); the graph is
+ * captured on private streams at first use and
  * captured again whenever dt, dx, amax_dev or a class's tile change.  A plan may be used
  * from one host thread at a time; hydro_plan_destroy waits for its work.
  */

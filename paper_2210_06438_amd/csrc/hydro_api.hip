@@ -336,9 +336,25 @@ int plan_launches(hydro_plan* p, double dt, double dx, double* amax, hipStream_t
   return HYDRO_OK;
 }
 
-// Record one step into the graph being captured on p->capture, one branch
-// per class.  Never returns early: a failed call still leaves every side
-// stream joined, so the caller can always end the capture.
+// Work-groups of one table launch of class c over n sub-grids (current tile).
+int class_groups(int c, int n) {
+  const int tile = g_tile[c].load(std::memory_order_relaxed);
+  const int B = c < 2 ? hydro::groups_per_subgrid<14>(tile)
+              : c < 4 ? hydro::groups_per_subgrid<18>(tile)
+                      : hydro::groups_per_subgrid<22>(tile);
+  return hydro::grid_for(n, B);
+}
+
+// A class becomes a branch of its own only when its grid is at least two
+// full rounds of resident work-groups (2 per CU on 256 CUs): a branch's
+// fork and join cost the step ~25 us, which only the overlap of large
+// launches (their partly filled last waves) pays back; small classes run in
+// sequence on the capture stream.
+constexpr int kBranchGroups = 1024;
+
+// Record one step into the graph being captured on p->capture.  Never
+// returns early: a failed call still leaves every side stream joined, so
+// the caller can always end the capture.
 int plan_capture_branches(hydro_plan* p, double dt, double dx, double* amax) {
   int rc = HYDRO_OK;
   auto hip = [&rc](hipError_t e, const char* what) {
@@ -346,23 +362,41 @@ int plan_capture_branches(hydro_plan* p, double dt, double dx, double* amax) {
       rc = fail(HYDRO_EHIP, "%s failed: %s", what, hipGetErrorString(e));
     return e == hipSuccess;
   };
-  const bool forked = hip(hipEventRecord(p->fork, p->capture), "hipEventRecord(fork)");
-  bool first = true;
+  bool big[kClasses] = {};
+  int nbig = 0;
+  for (int c = 0; c < kClasses; ++c)
+    if (p->num[c] && class_groups(c, p->num[c]) >= kBranchGroups) {
+      big[c] = true;
+      ++nbig;
+    }
+  bool done[kClasses] = {};
+  if (nbig >= 2 && hip(hipEventRecord(p->fork, p->capture), "hipEventRecord(fork)")) {
+    // the first large class on the capture stream, every other large class
+    // on a branch of its own (captured in class order: the graph starts its
+    // nodes in that order)
+    bool first = true;
+    for (int c = 0; c < kClasses; ++c) {
+      if (!big[c]) continue;
+      if (first) {
+        first = false;
+        done[c] = true;
+        if (rc == HYDRO_OK) rc = dispatch_table(c, p->table + p->off[c], p->num[c], dt, dx, amax, p->capture);
+        continue;
+      }
+      if (!hip(hipStreamWaitEvent(p->side[c], p->fork, 0), "hipStreamWaitEvent(fork)")) continue;
+      done[c] = true;
+      if (rc == HYDRO_OK) {
+        int r = dispatch_table(c, p->table + p->off[c], p->num[c], dt, dx, amax, p->side[c]);
+        if (r) rc = r;
+      }
+      if (hip(hipEventRecord(p->join[c], p->side[c]), "hipEventRecord(join)"))
+        hip(hipStreamWaitEvent(p->capture, p->join[c], 0), "hipStreamWaitEvent(join)");
+    }
+  }
+  // the rest in sequence on the capture stream
   for (int c = 0; c < kClasses; ++c) {
-    if (!p->num[c]) continue;
-    if (first) {
-      first = false;
-      if (rc == HYDRO_OK) rc = dispatch_table(c, p->table + p->off[c], p->num[c], dt, dx, amax, p->capture);
-      continue;
-    }
-    if (!forked || !hip(hipStreamWaitEvent(p->side[c], p->fork, 0), "hipStreamWaitEvent(fork)"))
-      continue;
-    if (rc == HYDRO_OK) {
-      int r = dispatch_table(c, p->table + p->off[c], p->num[c], dt, dx, amax, p->side[c]);
-      if (r) rc = r;
-    }
-    if (hip(hipEventRecord(p->join[c], p->side[c]), "hipEventRecord(join)"))
-      hip(hipStreamWaitEvent(p->capture, p->join[c], 0), "hipStreamWaitEvent(join)");
+    if (!p->num[c] || done[c]) continue;
+    if (rc == HYDRO_OK) rc = dispatch_table(c, p->table + p->off[c], p->num[c], dt, dx, amax, p->capture);
   }
   return rc;
 }

@@ -305,27 +305,43 @@ def test_batch_larger_than_a_staging_slot(dev, oracle_mod):
     del u_in, u_out
 
 
-def test_plan_graph_branches_match_eager_step(dev):
-    """A plan over all six (n, F) classes: its graph holds one branch per
-    class, and every replay (with eager work between them) is bitwise the
-    eager hydro_step result, outputs and amax."""
+MIXES = {
+    # every class small: the graph runs them in sequence
+    "six_small_classes": [((8, 6), 20), ((8, 11), 20), ((12, 6), 20), ((12, 11), 20),
+                          ((16, 6), 20), ((16, 11), 20)],
+    # two classes of >= 1024 work-groups (one becomes a side branch) and two
+    # small ones in sequence beside them
+    "two_large_classes": [((8, 6), 1024), ((16, 6), 128), ((12, 11), 5), ((8, 11), 3)],
+}
+
+
+@pytest.mark.parametrize("mix", sorted(MIXES))
+def test_plan_graph_matches_eager_step(dev, mix):
+    """A plan's graph (classes in sequence, or large classes as concurrent
+    branches) gives, on every replay with eager work between replays, bitwise
+    the eager hydro_step result: outputs and amax."""
     parts = []
-    for k, (n, nf) in enumerate([(8, 6), (8, 11), (12, 6), (12, 11), (16, 6), (16, 11)]):
-        U = workloads.random_smooth(20, n=n, nfields=nf, seed=1300 + k)
+    before = {(n, nf): hydroagg.get_tile(n, nf) for (n, nf), _ in MIXES[mix]}
+    for k, ((n, nf), cnt) in enumerate(MIXES[mix]):
+        U = workloads.random_smooth(cnt, n=n, nfields=nf, seed=1300 + k)
         u_in = torch.from_numpy(U).to(dev)
         parts.append((u_in, u_in.clone(), u_in.clone()))
-    count = 20 * len(parts)
+    count = sum(c for _, c in MIXES[mix])
     graph_descs = hydroagg.concat(*[hydroagg.subgrids(a, b) for a, b, _ in parts])
     eager_descs = hydroagg.concat(*[hydroagg.subgrids(a, c) for a, _, c in parts])
     amax_g = torch.zeros(count, dtype=torch.float64, device=dev)
     amax_e = torch.zeros(count, dtype=torch.float64, device=dev)
     dt, dx = 2e-3, 0.05
-    print("plan branches: 6 classes x 20 sub-grids", flush=True)
-    hydroagg.hydro_step(eager_descs, dt, dx, amax_e)
-    torch.cuda.synchronize()
-    plan = hydroagg.Plan(graph_descs)
-    stream = torch.cuda.current_stream()
+    print(f"plan graph: {mix}", flush=True)
+    plan = None
     try:
+        for (n, nf), _ in MIXES[mix]:
+            if mix == "two_large_classes":
+                hydroagg.set_tile(n, nf, 8)   # 8^3 blocks: 1024 work-groups per large class
+        hydroagg.hydro_step(eager_descs, dt, dx, amax_e)
+        torch.cuda.synchronize()
+        plan = hydroagg.Plan(graph_descs)
+        stream = torch.cuda.current_stream()
         for replay in range(3):
             for _, b, _ in parts:
                 b.fill_(-1.0)
@@ -337,4 +353,7 @@ def test_plan_graph_branches_match_eager_step(dev):
                 assert torch.equal(b[i], c[i]), f"replay {replay}"
             assert torch.equal(amax_g, amax_e), f"replay {replay}"
     finally:
-        plan.close()
+        for (n, nf), t in before.items():
+            hydroagg.set_tile(n, nf, t)
+        if plan is not None:
+            plan.close()
