@@ -85,7 +85,10 @@ int hydro_get_tile(int32_t n, int32_t nfields, int32_t *tile);
 
 /*
  * hydro_step -- one stage for `count` sub-grids (paper Section IV-B), as one
- * aggregated launch per (n, nfields) class present in the batch.
+ * aggregated launch per (n, nfields) class present in the batch; a batch of
+ * several classes of one field count with at most 8 sub-grids per class is
+ * ONE launch in which the classes run side by side (results bitwise those
+ * of the per-class launches).
  *   sg       host array of `count` descriptors (copied before return).
  *   dt       time-step, >= 0 and finite.  dt = 0 leaves the interior equal to
  *            u_in and still produces amax (used to pick the Courant dt).

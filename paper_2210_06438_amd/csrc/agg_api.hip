@@ -135,13 +135,22 @@ class HipExec {
     // it only after they finished.  Otherwise amax is combined in device
     // memory and copied back.
     double* amax = single ? sl.hamax_dev : sl.damax;
+    // Several classes of one field count go to one launch (classes side by
+    // side).
+    const bool mixed = hydro::api::mixed_eligible(num);
     if (!small)
       HIP_OK(hipMemcpyAsync(sl.dtab, sl.htab, sizeof(DevDesc) * n, hipMemcpyHostToDevice, st));
-    for (int c = 0; c < hydro::api::kNumClasses; ++c) {
-      if (!num[c]) continue;
-      int rc = small ? hydro::api::launch_class_args(c, sl.htab + off[c], num[c], dt, dx, amax, st)
-                     : hydro::api::launch_class(c, sl.dtab + off[c], num[c], dt, dx, amax, st);
+    if (mixed) {
+      // several classes of one field count: one launch, classes side by side
+      int rc = hydro::api::launch_mixed(num, off, sl.htab, sl.dtab, n, dt, dx, amax, st);
       if (rc) return rc;
+    } else {
+      for (int c = 0; c < hydro::api::kNumClasses; ++c) {
+        if (!num[c]) continue;
+        int rc = small ? hydro::api::launch_class_args(c, sl.htab + off[c], num[c], dt, dx, amax, st)
+                       : hydro::api::launch_class(c, sl.dtab + off[c], num[c], dt, dx, amax, st);
+        if (rc) return rc;
+      }
     }
     if (!single)
       HIP_OK(hipMemcpyAsync(sl.hamax, sl.damax, sizeof(double) * n, hipMemcpyDeviceToHost, st));

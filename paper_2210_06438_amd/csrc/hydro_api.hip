@@ -23,6 +23,8 @@
 #include "hydro_kernel.hpp"
 #include "hydro_lds8.hpp"
 #include "hydro_q4.hpp"
+#include "hydro_mixed.hpp"
+#include "internal.hpp"
 
 using hydro::ArgDescs;
 using hydro::DevDesc;
@@ -229,6 +231,22 @@ int step_chunk(DeviceState* st, const hydro_subgrid_t* sg, int count, int base,
   for (int c = 0; c < kClasses; ++c)
     if (per_class[c] > hydro::kArgDescs) need_table += per_class[c];
 
+  // A small batch of several classes of one field count: one launch with
+  // every descriptor in the kernel arguments.
+  if (need_table == 0 && hydro::api::mixed_eligible(per_class)) {
+    DevDesc host[kClasses * hydro::kArgDescs];
+    int off[kClasses], fill[kClasses], pos = 0;
+    for (int c = 0; c < kClasses; ++c) {
+      off[c] = fill[c] = pos;
+      pos += per_class[c];
+    }
+    for (int i = 0; i < count; ++i) {
+      const int c = class_of(sg[i].n, sg[i].nfields);
+      host[fill[c]++] = to_dev(sg[i], base + i);
+    }
+    return hydro::api::launch_mixed(per_class, off, host, nullptr, count, dt, dx, amax, stream);
+  }
+
   // Small classes: descriptors travel in the kernel arguments.
   for (int c = 0; c < kClasses; ++c) {
     if (per_class[c] == 0 || per_class[c] > hydro::kArgDescs) continue;
@@ -278,6 +296,85 @@ int step_chunk(DeviceState* st, const hydro_subgrid_t* sg, int count, int base,
 namespace hydro {
 namespace api {
 int class_of_task(int n, int nf) { return class_of(n, nf); }
+
+bool mixed_eligible(const int* num) {
+  int present = 0, f = -1;
+  for (int c = 0; c < kClasses; ++c) {
+    if (!num[c]) continue;
+    ++present;
+    if (f < 0)
+      f = c & 1;
+    else if ((c & 1) != f)
+      return false;
+  }
+  return present >= 2;
+}
+
+int launch_mixed(const int* num, const int* off, const DevDesc* host, const DevDesc* table,
+                 int n, double dt, double dx, double* amax, hipStream_t s) {
+  if (!mixed_eligible(num)) return fail(HYDRO_EINVAL, "batch is not a mixed batch of one field count");
+  int f = 0;
+  bool args = true;
+  for (int c = 0; c < kClasses; ++c)
+    if (num[c]) {
+      f = c & 1;
+      args = args && num[c] <= kArgDescs;
+    }
+  const bool f11 = f == 1;
+  if (!args && !table) return fail(HYDRO_EINVAL, "%d descriptors need a device table", n);
+  if (args) {
+    MixedArgs m;
+    memset(&m, 0, sizeof m);
+    int start = 0, first = 0;
+    for (int e = 0; e < kMixedSegs; ++e) {
+      const int c = 2 * e + f;
+      if (!num[c]) continue;
+      const int path = 2 * e + (g_tile[c].load(std::memory_order_relaxed) == 4 ? 1 : 0);
+      m.seg[m.nseg++] = MixedSeg{start, num[c], path, first};
+      for (int i = 0; i < num[c]; ++i) m.d[first + i] = host[off[c] + i];
+      start += num[c] * path_groups(path);
+      first += num[c];
+    }
+    if (amax) {
+      hipLaunchKernelGGL(amax_zero_mixed, dim3(1), dim3(64), 0, s, m, first, amax);
+      HIP_TRY(hipGetLastError());
+    }
+    if (f11)
+      hipLaunchKernelGGL(hydro_mixed_arg_kernel<11>, dim3(start), dim3(Lds8::kThreads), 0, s, m,
+                         dt, dx, amax);
+    else
+      hipLaunchKernelGGL(hydro_mixed_arg_kernel<6>, dim3(start), dim3(Lds8::kThreads), 0, s, m,
+                         dt, dx, amax);
+    HIP_TRY(hipGetLastError());
+    return HYDRO_OK;
+  }
+  MixedTable m;
+  memset(&m, 0, sizeof m);
+  int start = 0;
+  for (int e = 0; e < kMixedSegs; ++e) {
+    const int c = 2 * e + f;
+    if (!num[c]) continue;
+    const int path = 2 * e + (g_tile[c].load(std::memory_order_relaxed) == 4 ? 1 : 0);
+    m.table[m.nseg] = table + off[c];
+    m.seg[m.nseg++] = MixedSeg{start, num[c], path, 0};
+    // segments start at multiples of 8: a sub-grid's work-groups stay on one XCD
+    start += grid_for(num[c], path_groups(path));
+    start = (start + 7) / 8 * 8;
+  }
+  if (amax) {
+    hipLaunchKernelGGL(amax_zero_table, dim3((n + 255) / 256), dim3(256), 0, s, table, n, amax);
+    HIP_TRY(hipGetLastError());
+  }
+  if (f11)
+    hipLaunchKernelGGL(hydro_mixed_kernel<11>, dim3(start), dim3(Lds8::kThreads), 0, s, m, dt, dx,
+                       amax);
+  else
+    hipLaunchKernelGGL(hydro_mixed_kernel<6>, dim3(start), dim3(Lds8::kThreads), 0, s, m, dt, dx,
+                       amax);
+  HIP_TRY(hipGetLastError());
+  return HYDRO_OK;
+}
+
 int validate_batch(const hydro_subgrid_t* sg, int32_t count, double dt, double dx) {
   return validate(sg, count, dt, dx);
 }

@@ -53,6 +53,17 @@ struct Lds8 {
   static constexpr long FS = (long)M * M * M;
 };
 
+// The LDS arrays of a work-group, at file scope so that every step function
+// (both tiles, every edge and field count) uses the same four objects: a
+// kernel that holds several of them -- one path per shape class -- allocates
+// them once.  Sized for the largest user (the 8^3 tile with 11 fields).
+// tin: interiors of the staged fields.  acc: x+y flux differences (two
+// atomic adds onto zero per cell).  held: the z lanes' U - lambda*dF_z.
+__shared__ double lds_tin[6 * Lds8::P];
+__shared__ double lds_acc[5 * Lds8::P];
+__shared__ double lds_held[5 * Lds8::P];
+__shared__ double lds_red[3];
+
 // LDS index of interior cell (x, y, z), 0 <= x, y, z < 8.
 __device__ __forceinline__ int lcell(int x, int y, int z) {
   return z * Lds8::PS + y * Lds8::RS + x;
@@ -266,12 +277,11 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int
   constexpr int P = Lds8::P;
   constexpr int NP = F - 5;              // passive fields
   constexpr int NT = NP > 5 ? NP : 5;    // regions of the staged-interior array
-  // tin: interiors of the staged fields.  acc: x+y flux differences (two
-  // atomic adds onto zero per cell).  held: the z lanes' U - lambda*dF_z.
-  __shared__ double tin[NT * P];
-  __shared__ double acc[5 * P];
-  __shared__ double held[5 * P];
-  __shared__ double red[3];
+  static_assert(NT * P <= 6 * Lds8::P, "staged interiors exceed lds_tin");
+  double* const tin = lds_tin;
+  double* const acc = lds_acc;
+  double* const held = lds_held;
+  double* const red = lds_red;
 
   const int t = threadIdx.x;
   const int dir = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform

@@ -126,10 +126,12 @@ __device__ __forceinline__ void q4_step(const DevDesc& d, int group, double dt, 
   constexpr int P = Q4::P;
   constexpr int NP = F - 5;
   constexpr int NT = NP > 5 ? NP : 5;
-  __shared__ double tin[NT * P];
-  __shared__ double acc[5 * P];
-  __shared__ double held[5 * P];
-  __shared__ double red[3];
+  // the file-scope LDS arrays of hydro_lds8.hpp (same roles)
+  static_assert(NT * P <= 6 * Lds8::P && 5 * P <= 5 * Lds8::P, "q4 arrays exceed the LDS arrays");
+  double* const tin = lds_tin;
+  double* const acc = lds_acc;
+  double* const held = lds_held;
+  double* const red = lds_red;
 
   const int t = threadIdx.x;
   const int dir = __builtin_amdgcn_readfirstlane(t >> 6);

@@ -34,5 +34,18 @@ bool class_single_block(int cls);
 int launch_class_args(int cls, const DevDesc* host, int n, double dt, double dx, double* amax,
                       hipStream_t s);
 
+// True when a batch with per-class counts num[] can be one launch_mixed:
+// at least two classes present, all of one field count.
+bool mixed_eligible(const int* num);
+
+// One launch for every class of such a batch (hydro_mixed.hpp): class c has
+// num[c] sub-grids whose descriptors start at index off[c], n in all.  When
+// every class has at most kArgDescs they are read from `host` into the
+// kernel arguments; otherwise from the device table `table` (the whole
+// batch, classes contiguous).  amax slots (if amax is not NULL) are zeroed
+// first, on the same stream.
+int launch_mixed(const int* num, const int* off, const DevDesc* host, const DevDesc* table,
+                 int n, double dt, double dx, double* amax, hipStream_t s);
+
 }  // namespace api
 }  // namespace hydro

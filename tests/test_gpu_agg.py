@@ -199,3 +199,39 @@ def test_tile_sweep_chooses_and_applies(dev):
     finally:
         for (n, f), t in before.items():
             hydroagg.set_tile(n, f, t)
+
+
+@pytest.mark.parametrize("tiles", [None, 4, 8])
+def test_aggregator_mixed_batch_table_form(dev, tiles):
+    """One aggregated batch of more than 8 sub-grids per class (8^3, 12^3,
+    16^3; descriptors in a device table, one multi-class launch): every task
+    is bitwise what it is stepped alone."""
+    keys = [(n, 11) for n in (8, 12, 16)]
+    before = {k: hydroagg.get_tile(*k) for k in keys}
+    print(f"agg mixed table: tiles={tiles}", flush=True)
+    try:
+        if tiles is not None:
+            for k in keys:
+                hydroagg.set_tile(*k, tiles)
+        dt, dx = 0.002, 0.05
+        Us = {n: workloads.random_smooth(c, n=n, nfields=11, seed=1500 + n)
+              for n, c in ((8, 10), (12, 9), (16, 9))}
+        ins = {n: torch.from_numpy(U).to(dev) for n, U in Us.items()}
+        outs = {n: t.clone() for n, t in ins.items()}
+        descs = {n: hydroagg.subgrids(ins[n], outs[n])[0] for n in Us}
+        agg = hydroagg.Aggregator(64, timeout_us=-1.0, n_streams=1, flush_when_idle=False)
+        tickets = [(n, i, agg.submit(descs[n][i], dt, dx)) for n in Us for i in range(len(Us[n]))]
+        agg.flush()
+        got = {(n, i): agg.wait(t) for n, i, t in tickets}
+        st = agg.stats()
+        agg.close()
+        torch.cuda.synchronize()
+        assert st["batches"] == 1 and st["launched"] == 28
+        for n, U in Us.items():
+            ref, ref_a = alone(U, dt, dx)
+            O = outs[n].cpu().numpy()
+            for i in range(len(U)):
+                assert np.array_equal(O[i], ref[i]) and got[(n, i)] == ref_a[i], (n, i)
+    finally:
+        for k, t in before.items():
+            hydroagg.set_tile(*k, t)

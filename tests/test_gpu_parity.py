@@ -357,3 +357,52 @@ def test_plan_graph_matches_eager_step(dev, mix):
             hydroagg.set_tile(n, nf, t)
         if plan is not None:
             plan.close()
+
+
+TILE_SETS = {"default": None, "all_4": 4, "all_8": 8}
+
+
+def _with_tiles(tiles, fn):
+    keys = [(n, nf) for n in (8, 12, 16) for nf in (6, 11)]
+    before = {k: hydroagg.get_tile(*k) for k in keys}
+    try:
+        if tiles is not None:
+            for k in keys:
+                hydroagg.set_tile(*k, tiles)
+        return fn()
+    finally:
+        for k, t in before.items():
+            hydroagg.set_tile(*k, t)
+
+
+@pytest.mark.parametrize("tiles", sorted(TILE_SETS))
+@pytest.mark.parametrize("nf", [6, 11])
+def test_small_mixed_batch_is_one_launch_bitwise_alone(dev, oracle_mod, tiles, nf):
+    """A small batch of 8^3, 12^3 and 16^3 sub-grids of one field count is
+    one multi-class launch; every sub-grid is bitwise what it is stepped
+    alone (its class kernel) and matches the oracle."""
+    counts = {8: 3, 12: 2, 16: 2}
+    dt, dx = 2e-3, 0.05
+    print(f"mixed small: F={nf} tiles={tiles}", flush=True)
+
+    def run():
+        out = {}
+        parts = {}
+        for n, c in counts.items():
+            U = workloads.random_smooth(c, n=n, nfields=nf, seed=1400 + n + nf)
+            t = torch.from_numpy(U).to(dev)
+            parts[n] = (U, t, t.clone())
+        amax = torch.zeros(sum(counts.values()), dtype=torch.float64, device=dev)
+        hydroagg.hydro_step(hydroagg.concat(*[hydroagg.subgrids(a, b) for _, a, b in parts.values()]),
+                            dt, dx, amax)
+        torch.cuda.synchronize()
+        k = 0
+        for n, (U, a, b) in parts.items():
+            got = b.cpu().numpy()
+            ref, ref_a = run_gpu(U, dt, dx, each=True)   # one launch per sub-grid
+            assert np.array_equal(interior(got, n), interior(ref, n)), n
+            assert np.array_equal(amax.cpu().numpy()[k:k + len(U)], ref_a), n
+            o, oa = oracle_mod.step(U, dt, dx)
+            assert np.all(normwise(interior(got, n), interior(o, n)) <= TOL)
+            k += len(U)
+    _with_tiles(TILE_SETS[tiles], run)
