@@ -321,6 +321,7 @@ int launch_mixed(const int* num, const int* off, const DevDesc* host, const DevD
       args = args && num[c] <= kArgDescs;
     }
   const bool f11 = f == 1;
+  if (!host) args = false;
   if (!args && !table) return fail(HYDRO_EINVAL, "%d descriptors need a device table", n);
   if (args) {
     MixedArgs m;
@@ -350,19 +351,20 @@ int launch_mixed(const int* num, const int* off, const DevDesc* host, const DevD
   }
   MixedTable m;
   memset(&m, 0, sizeof m);
-  int start = 0;
+  int start = 0, most = 0;
   for (int e = 0; e < kMixedSegs; ++e) {
     const int c = 2 * e + f;
     if (!num[c]) continue;
     const int path = 2 * e + (g_tile[c].load(std::memory_order_relaxed) == 4 ? 1 : 0);
     m.table[m.nseg] = table + off[c];
     m.seg[m.nseg++] = MixedSeg{start, num[c], path, 0};
+    most = num[c] > most ? num[c] : most;
     // segments start at multiples of 8: a sub-grid's work-groups stay on one XCD
     start += grid_for(num[c], path_groups(path));
     start = (start + 7) / 8 * 8;
   }
   if (amax) {
-    hipLaunchKernelGGL(amax_zero_table, dim3((n + 255) / 256), dim3(256), 0, s, table, n, amax);
+    hipLaunchKernelGGL(amax_zero_mixed_table, dim3((most + 255) / 256), dim3(256), 0, s, m, amax);
     HIP_TRY(hipGetLastError());
   }
   if (f11)
@@ -490,9 +492,20 @@ int plan_capture_branches(hydro_plan* p, double dt, double dx, double* amax) {
         hip(hipStreamWaitEvent(p->capture, p->join[c], 0), "hipStreamWaitEvent(join)");
     }
   }
-  // the rest in sequence on the capture stream
+  // the rest on the capture stream: one multi-class launch when they are
+  // several classes of one field count, else in sequence
+  int rest[kClasses] = {0};
+  for (int c = 0; c < kClasses; ++c)
+    if (!done[c]) rest[c] = p->num[c];
+  if (hydro::api::mixed_eligible(rest)) {
+    int n = 0;
+    for (int c = 0; c < kClasses; ++c) n += rest[c];
+    if (rc == HYDRO_OK)
+      rc = hydro::api::launch_mixed(rest, p->off, nullptr, p->table, n, dt, dx, amax, p->capture);
+    return rc;
+  }
   for (int c = 0; c < kClasses; ++c) {
-    if (!p->num[c] || done[c]) continue;
+    if (!rest[c]) continue;
     if (rc == HYDRO_OK) rc = dispatch_table(c, p->table + p->off[c], p->num[c], dt, dx, amax, p->capture);
   }
   return rc;

@@ -150,6 +150,14 @@ __global__ void __launch_bounds__(Lds8::kThreads, 2)
   }
 }
 
+// amax slots of a table-form batch set to zero before the launch: lane i of
+// the grid clears slot i of every segment that has one.
+__global__ void amax_zero_mixed_table(MixedTable m, double* __restrict__ amax_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int j = 0; j < m.nseg; ++j)
+    if (i < m.seg[j].count) amax_out[m.table[j][i].index] = 0.0;
+}
+
 // amax slots of an argument-form batch set to zero before the launch (one
 // work-group of 64 lanes).
 __global__ void amax_zero_mixed(MixedArgs m, int count, double* __restrict__ amax_out) {

@@ -40,10 +40,10 @@ bool mixed_eligible(const int* num);
 
 // One launch for every class of such a batch (hydro_mixed.hpp): class c has
 // num[c] sub-grids whose descriptors start at index off[c], n in all.  When
-// every class has at most kArgDescs they are read from `host` into the
-// kernel arguments; otherwise from the device table `table` (the whole
-// batch, classes contiguous).  amax slots (if amax is not NULL) are zeroed
-// first, on the same stream.
+// `host` is given and every class has at most kArgDescs they are read from
+// `host` into the kernel arguments; otherwise from the device table `table`
+// (table + off[c] for class c).  amax slots (if amax is not NULL) are
+// zeroed first, on the same stream.
 int launch_mixed(const int* num, const int* off, const DevDesc* host, const DevDesc* table,
                  int n, double dt, double dx, double* amax, hipStream_t s);
 

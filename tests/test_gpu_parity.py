@@ -310,8 +310,11 @@ MIXES = {
     "six_small_classes": [((8, 6), 20), ((8, 11), 20), ((12, 6), 20), ((12, 11), 20),
                           ((16, 6), 20), ((16, 11), 20)],
     # two classes of >= 1024 work-groups (one becomes a side branch) and two
-    # small ones in sequence beside them
+    # small ones of one field count (one multi-class launch) beside them
     "two_large_classes": [((8, 6), 1024), ((16, 6), 128), ((12, 11), 5), ((8, 11), 3)],
+    # small classes of one field count: one multi-class launch from the
+    # plan's device table (the eager step passes them in the arguments)
+    "three_small_one_field_count": [((8, 11), 5), ((12, 11), 4), ((16, 11), 3)],
 }
 
 
