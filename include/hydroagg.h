@@ -86,9 +86,9 @@ int hydro_get_tile(int32_t n, int32_t nfields, int32_t *tile);
 /*
  * hydro_step -- one stage for `count` sub-grids (paper Section IV-B), as one
  * aggregated launch per (n, nfields) class present in the batch; a batch of
- * several classes of one field count with at most 8 sub-grids per class is
- * ONE launch in which the classes run side by side (results bitwise those
- * of the per-class launches).
+ * several classes of one field count whose classes are each below 1024
+ * work-groups is ONE launch in which the classes run side by side (results
+ * bitwise those of the per-class launches).
  *   sg       host array of `count` descriptors (copied before return).
  *   dt       time-step, >= 0 and finite.  dt = 0 leaves the interior equal to
  *            u_in and still produces amax (used to pick the Courant dt).
@@ -124,8 +124,8 @@ int hydro_step_each(const hydro_subgrid_t *sg, int32_t count, double dt,
  * that step the same set of sub-grids repeatedly (every stage of a time-step
  * on device-resident state).  hydro_plan_create copies `sg` into a
  * plan-owned device table (this allocates, so it belongs to set-up, not to
- * the step path).  hydro_plan_step then only launches kernels: one per
- * (n, nfields) class, with the results and errors of hydro_step.
+ * the step path).  hydro_plan_step then only launches kernels, grouped as
+ * in hydro_step, with its results and errors.
  * hydro_plan_launch_graph runs the same launches as ONE hipGraph launch on
  * `stream`; classes of at least 1024 work-groups become independent
  * branches of the graph and run concurrently, smaller ones run in sequence

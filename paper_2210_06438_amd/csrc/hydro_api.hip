@@ -222,6 +222,22 @@ DevDesc to_dev(const hydro_subgrid_t& s, int index) {
   return d;
 }
 
+// Work-groups of one table launch of class c over n sub-grids (current tile).
+int class_groups(int c, int n) {
+  const int tile = g_tile[c].load(std::memory_order_relaxed);
+  const int B = c < 2 ? hydro::groups_per_subgrid<14>(tile)
+              : c < 4 ? hydro::groups_per_subgrid<18>(tile)
+                      : hydro::groups_per_subgrid<22>(tile);
+  return hydro::grid_for(n, B);
+}
+
+// A class becomes a branch of its own only when its grid is at least two
+// full rounds of resident work-groups (2 per CU on 256 CUs): a branch's
+// fork and join cost the step ~25 us, which only the overlap of large
+// launches (their partly filled last waves) pays back; small classes run in
+// sequence on the capture stream.
+constexpr int kBranchGroups = 1024;
+
 // One chunk of at most kSlotCap sub-grids starting at batch offset `base`.
 int step_chunk(DeviceState* st, const hydro_subgrid_t* sg, int count, int base,
                double dt, double dx, double* amax, hipStream_t stream) {
@@ -245,6 +261,38 @@ int step_chunk(DeviceState* st, const hydro_subgrid_t* sg, int count, int base,
       host[fill[c]++] = to_dev(sg[i], base + i);
     }
     return hydro::api::launch_mixed(per_class, off, host, nullptr, count, dt, dx, amax, stream);
+  }
+  // A larger one whose classes are all below kBranchGroups work-groups: one
+  // launch from a device table (classes side by side).  Larger classes keep
+  // their own launches: their grids overlap little, and the table form of
+  // the multi-class kernel spills a few registers.
+  bool fuse = hydro::api::mixed_eligible(per_class);
+  for (int c = 0; c < kClasses && fuse; ++c)
+    fuse = !per_class[c] || class_groups(c, per_class[c]) < kBranchGroups;
+  if (fuse) {
+    Slot* slot;
+    {
+      std::lock_guard<std::mutex> lk(st->mu);
+      slot = &st->slots[st->next];
+      st->next = (st->next + 1) % kSlots;
+    }
+    if (slot->used) HIP_TRY(hipEventSynchronize(slot->done));
+    int off[kClasses], fill[kClasses], pos = 0;
+    for (int c = 0; c < kClasses; ++c) {
+      off[c] = fill[c] = pos;
+      pos += per_class[c];
+    }
+    for (int i = 0; i < count; ++i) {
+      const int c = class_of(sg[i].n, sg[i].nfields);
+      slot->host[fill[c]++] = to_dev(sg[i], base + i);
+    }
+    HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, sizeof(DevDesc) * count,
+                           hipMemcpyHostToDevice, stream));
+    int rc = hydro::api::launch_mixed(per_class, off, nullptr, slot->dev, count, dt, dx, amax, stream);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(slot->done, stream));
+    slot->used = true;
+    return HYDRO_OK;
   }
 
   // Small classes: descriptors travel in the kernel arguments.
@@ -427,6 +475,12 @@ struct hydro_plan {
 namespace {
 
 int plan_launches(hydro_plan* p, double dt, double dx, double* amax, hipStream_t s) {
+  // several classes of one field count, all below kBranchGroups work-groups:
+  // one multi-class launch (as hydro_step does)
+  bool fuse = hydro::api::mixed_eligible(p->num);
+  for (int c = 0; c < kClasses && fuse; ++c)
+    fuse = !p->num[c] || class_groups(c, p->num[c]) < kBranchGroups;
+  if (fuse) return hydro::api::launch_mixed(p->num, p->off, nullptr, p->table, p->count, dt, dx, amax, s);
   for (int c = 0; c < kClasses; ++c) {
     if (!p->num[c]) continue;
     int rc = dispatch_table(c, p->table + p->off[c], p->num[c], dt, dx, amax, s);
@@ -434,22 +488,6 @@ int plan_launches(hydro_plan* p, double dt, double dx, double* amax, hipStream_t
   }
   return HYDRO_OK;
 }
-
-// Work-groups of one table launch of class c over n sub-grids (current tile).
-int class_groups(int c, int n) {
-  const int tile = g_tile[c].load(std::memory_order_relaxed);
-  const int B = c < 2 ? hydro::groups_per_subgrid<14>(tile)
-              : c < 4 ? hydro::groups_per_subgrid<18>(tile)
-                      : hydro::groups_per_subgrid<22>(tile);
-  return hydro::grid_for(n, B);
-}
-
-// A class becomes a branch of its own only when its grid is at least two
-// full rounds of resident work-groups (2 per CU on 256 CUs): a branch's
-// fork and join cost the step ~25 us, which only the overlap of large
-// launches (their partly filled last waves) pays back; small classes run in
-// sequence on the capture stream.
-constexpr int kBranchGroups = 1024;
 
 // Record one step into the graph being captured on p->capture.  Never
 // returns early: a failed call still leaves every side stream joined, so
@@ -492,20 +530,23 @@ int plan_capture_branches(hydro_plan* p, double dt, double dx, double* amax) {
         hip(hipStreamWaitEvent(p->capture, p->join[c], 0), "hipStreamWaitEvent(join)");
     }
   }
-  // the rest on the capture stream: one multi-class launch when they are
-  // several classes of one field count, else in sequence
-  int rest[kClasses] = {0};
+  // the rest on the capture stream: the small classes (below kBranchGroups)
+  // as one multi-class launch when they are several of one field count, the
+  // others one launch each
+  int small[kClasses] = {0};
   for (int c = 0; c < kClasses; ++c)
-    if (!done[c]) rest[c] = p->num[c];
-  if (hydro::api::mixed_eligible(rest)) {
+    if (!done[c] && p->num[c] && !big[c]) small[c] = p->num[c];
+  if (hydro::api::mixed_eligible(small)) {
     int n = 0;
-    for (int c = 0; c < kClasses; ++c) n += rest[c];
+    for (int c = 0; c < kClasses; ++c) {
+      n += small[c];
+      if (small[c]) done[c] = true;
+    }
     if (rc == HYDRO_OK)
-      rc = hydro::api::launch_mixed(rest, p->off, nullptr, p->table, n, dt, dx, amax, p->capture);
-    return rc;
+      rc = hydro::api::launch_mixed(small, p->off, nullptr, p->table, n, dt, dx, amax, p->capture);
   }
   for (int c = 0; c < kClasses; ++c) {
-    if (!rest[c]) continue;
+    if (!p->num[c] || done[c]) continue;
     if (rc == HYDRO_OK) rc = dispatch_table(c, p->table + p->off[c], p->num[c], dt, dx, amax, p->capture);
   }
   return rc;

@@ -315,6 +315,9 @@ MIXES = {
     # small classes of one field count: one multi-class launch from the
     # plan's device table (the eager step passes them in the arguments)
     "three_small_one_field_count": [((8, 11), 5), ((12, 11), 4), ((16, 11), 3)],
+    # one large class alone (no branch: it is the only one) beside one
+    # multi-class launch of two small ones
+    "one_large_two_small": [((8, 11), 1100), ((12, 11), 5), ((16, 11), 3)],
 }
 
 
@@ -339,8 +342,8 @@ def test_plan_graph_matches_eager_step(dev, mix):
     plan = None
     try:
         for (n, nf), _ in MIXES[mix]:
-            if mix == "two_large_classes":
-                hydroagg.set_tile(n, nf, 8)   # 8^3 blocks: 1024 work-groups per large class
+            if mix in ("two_large_classes", "one_large_two_small"):
+                hydroagg.set_tile(n, nf, 8)   # 8^3 blocks: >= 1024 work-groups per large class
         hydroagg.hydro_step(eager_descs, dt, dx, amax_e)
         torch.cuda.synchronize()
         plan = hydroagg.Plan(graph_descs)
@@ -378,15 +381,20 @@ def _with_tiles(tiles, fn):
             hydroagg.set_tile(*k, t)
 
 
+MIXED_COUNTS = {"arguments": {8: 3, 12: 2, 16: 2}, "table": {8: 13, 12: 10, 16: 9}}
+
+
 @pytest.mark.parametrize("tiles", sorted(TILE_SETS))
 @pytest.mark.parametrize("nf", [6, 11])
-def test_small_mixed_batch_is_one_launch_bitwise_alone(dev, oracle_mod, tiles, nf):
-    """A small batch of 8^3, 12^3 and 16^3 sub-grids of one field count is
-    one multi-class launch; every sub-grid is bitwise what it is stepped
-    alone (its class kernel) and matches the oracle."""
-    counts = {8: 3, 12: 2, 16: 2}
+@pytest.mark.parametrize("form", sorted(MIXED_COUNTS))
+def test_mixed_batch_is_one_launch_bitwise_alone(dev, oracle_mod, tiles, nf, form):
+    """A batch of 8^3, 12^3 and 16^3 sub-grids of one field count is one
+    multi-class launch (descriptors in the kernel arguments up to 8 per
+    class, else in a device table); every sub-grid is bitwise what it is
+    stepped alone (its class kernel) and matches the oracle."""
+    counts = MIXED_COUNTS[form]
     dt, dx = 2e-3, 0.05
-    print(f"mixed small: F={nf} tiles={tiles}", flush=True)
+    print(f"mixed: form={form} F={nf} tiles={tiles}", flush=True)
 
     def run():
         out = {}
