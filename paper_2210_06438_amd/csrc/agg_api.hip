@@ -59,8 +59,9 @@ class HipExec {
     for (Slot& sl : slots_) {
       HIP_OK(hipHostMalloc((void**)&sl.htab, sizeof(DevDesc) * cap_, hipHostMallocDefault));
       HIP_OK(hipMalloc((void**)&sl.dtab, sizeof(DevDesc) * cap_));
-      HIP_OK(hipMalloc((void**)&sl.damax, sizeof(double) * cap_));
-      HIP_OK(hipHostMalloc((void**)&sl.hamax, sizeof(double) * cap_, hipHostMallocDefault));
+      HIP_OK(hipHostMalloc((void**)&sl.hamax, sizeof(double) * cap_ * hydro::kAmaxParts,
+                           hipHostMallocDefault));
+      sl.parts.assign((size_t)cap_, 0);
       HIP_OK(hipHostGetDevicePointer((void**)&sl.hamax_dev, sl.hamax, 0));
     }
     return HYDRO_OK;
@@ -72,7 +73,6 @@ class HipExec {
       if (sl.htab) (void)hipHostFree(sl.htab);
       if (sl.hamax) (void)hipHostFree(sl.hamax);
       if (sl.dtab) (void)hipFree(sl.dtab);
-      if (sl.damax) (void)hipFree(sl.damax);
     }
     slots_.clear();
     if (flags_) (void)hipHostFree(flags_);
@@ -119,41 +119,33 @@ class HipExec {
       d.index = i;
     }
     hipStream_t st = streams_[s];
-    // Small batches (at most kArgDescs tasks of every class) carry their
-    // descriptors in the kernel arguments: one stream operation fewer, which
-    // is most of a lightly loaded task's latency.
-    bool small = true, single = true;
-    for (int c = 0; c < hydro::api::kNumClasses; ++c) {
-      small = small && num[c] <= hydro::kArgDescs;
-      single = single && (num[c] == 0 || hydro::api::class_single_block(c));
-    }
-    // When every sub-grid is one work-group, each amax is a plain store and
-    // goes straight to the slot's pinned host array (device-accessible); the
-    // completion word below is written after the kernels, so the host reads
-    // it only after they finished.  Otherwise amax is combined in device
-    // memory and copied back.
-    double* amax = single ? sl.hamax_dev : sl.damax;
-    // Several classes of one field count go to one launch (classes side by
-    // side).
-    const bool mixed = hydro::api::mixed_eligible(num);
+    // One launch per field count present (hydro_mixed.hpp: its classes side
+    // by side), descriptors in the kernel arguments when every class has at
+    // most kArgDescs, else in the slot's device table.  Every work-group
+    // stores its amax partial straight into the slot's pinned host array
+    // (device-accessible) with a plain store: no zeroing, no atomics, no
+    // copy back; the completion word below is written after the kernels, so
+    // the host reads the partials only after they finished.
+    bool small = true;
+    for (int c = 0; c < hydro::api::kNumClasses; ++c) small = small && num[c] <= hydro::kArgDescs;
     if (!small)
       HIP_OK(hipMemcpyAsync(sl.dtab, sl.htab, sizeof(DevDesc) * n, hipMemcpyHostToDevice, st));
-    if (mixed) {
-      // several classes of one field count: one launch, classes side by side
-      int rc = hydro::api::launch_mixed(num, off, sl.htab, sl.dtab, n, dt, dx, amax, st);
-      if (rc) return rc;
-    } else {
-      for (int c = 0; c < hydro::api::kNumClasses; ++c) {
-        if (!num[c]) continue;
-        int rc = small ? hydro::api::launch_class_args(c, sl.htab + off[c], num[c], dt, dx, amax, st)
-                       : hydro::api::launch_class(c, sl.dtab + off[c], num[c], dt, dx, amax, st);
-        if (rc) return rc;
+    int groups[hydro::api::kNumClasses] = {0};
+    for (int f = 0; f < 2; ++f) {
+      int numf[hydro::api::kNumClasses] = {0}, nf = 0;
+      for (int c = f; c < hydro::api::kNumClasses; c += 2) {
+        numf[c] = num[c];
+        nf += num[c];
       }
+      if (!nf) continue;
+      int rc = hydro::api::launch_mixed(numf, off, sl.htab, sl.dtab, nf, dt, dx, sl.hamax_dev, st,
+                                        true, groups);
+      if (rc) return rc;
     }
-    if (!single)
-      HIP_OK(hipMemcpyAsync(sl.hamax, sl.damax, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    for (int i = 0; i < n; ++i)
+      sl.parts[i] = (uint8_t)groups[hydro::api::class_of_task(t[i].n, t[i].nfields)];
     // Completion word: the stream stores the batch id into pinned host memory
-    // after the amax copy, so polling completion is a memory read, not a
+    // after the kernels, so polling completion is a memory read, not a
     // runtime call, and blocking waits spin on it (no event per batch: each
     // runtime call is ~2 us of the serving thread's time).
     HIP_OK(hipStreamWriteValue64(st, &flags_[k], batch, 0));
@@ -185,8 +177,7 @@ class HipExec {
       std::copy(r->second.begin(), r->second.end(), amax);
       return;
     }
-    Slot& sl = slots_[live_.at(batch)];
-    std::copy(sl.hamax, sl.hamax + sl.n, amax);
+    reduce(slots_[live_.at(batch)], amax);
   }
 
   void release(uint64_t batch) {
@@ -206,13 +197,23 @@ class HipExec {
   struct Slot {
     DevDesc* htab = nullptr;
     DevDesc* dtab = nullptr;
-    double* damax = nullptr;
-    double* hamax = nullptr;
+    double* hamax = nullptr;      // kAmaxParts amax partials per task (pinned)
     double* hamax_dev = nullptr;  // the device's address of hamax
+    std::vector<uint8_t> parts;   // partials written for each task
     bool busy = false, finished = false;
     int stream = 0, n = 0;
     uint64_t batch = 0;
   };
+
+  // Task i's amax: the largest of its work-groups' partials.
+  static void reduce(const Slot& sl, double* amax) {
+    for (int i = 0; i < sl.n; ++i) {
+      const double* p = sl.hamax + (size_t)i * hydro::kAmaxParts;
+      double m = p[0];
+      for (int b = 1; b < sl.parts[i]; ++b) m = std::max(m, p[b]);
+      amax[i] = m;
+    }
+  }
 
   bool finished(int k) {
     Slot& sl = slots_[k];
@@ -255,7 +256,9 @@ class HipExec {
       const int rc = spin(live_.at(b));
       if (rc) return rc;
     }
-    retired_[b] = std::vector<double>(sl.hamax, sl.hamax + sl.n);
+    std::vector<double> a((size_t)sl.n);
+    reduce(sl, a.data());
+    retired_[b] = std::move(a);
     sl.busy = false;
     live_.erase(b);
     order_.pop_front();

@@ -359,91 +359,93 @@ bool mixed_eligible(const int* num) {
 }
 
 int launch_mixed(const int* num, const int* off, const DevDesc* host, const DevDesc* table,
-                 int n, double dt, double dx, double* amax, hipStream_t s) {
-  if (!mixed_eligible(num)) return fail(HYDRO_EINVAL, "batch is not a mixed batch of one field count");
-  int f = 0;
-  bool args = true;
+                 int n, double dt, double dx, double* amax, hipStream_t s, bool parts,
+                 int* groups) {
+  int f = -1, present = 0;
+  bool args = host != nullptr;
   for (int c = 0; c < kClasses; ++c)
     if (num[c]) {
+      if (f >= 0 && (c & 1) != f) return fail(HYDRO_EINVAL, "multi-class launch of two field counts");
       f = c & 1;
+      ++present;
       args = args && num[c] <= kArgDescs;
     }
-  const bool f11 = f == 1;
-  if (!host) args = false;
+  if (present < (parts ? 1 : 2)) return fail(HYDRO_EINVAL, "multi-class launch of %d classes", present);
   if (!args && !table) return fail(HYDRO_EINVAL, "%d descriptors need a device table", n);
+  const bool f11 = f == 1;
+  // segments in edge order; a class's path from its current tile
+  int path[kMixedSegs], cls[kMixedSegs], nseg = 0;
+  for (int e = 0; e < kMixedSegs; ++e) {
+    const int c = 2 * e + f;
+    if (!num[c]) continue;
+    cls[nseg] = c;
+    path[nseg++] = 2 * e + (g_tile[c].load(std::memory_order_relaxed) == 4 ? 1 : 0);
+    if (groups) groups[c] = path_groups(path[nseg - 1]);
+  }
   if (args) {
     MixedArgs m;
     memset(&m, 0, sizeof m);
     int start = 0, first = 0;
-    for (int e = 0; e < kMixedSegs; ++e) {
-      const int c = 2 * e + f;
-      if (!num[c]) continue;
-      const int path = 2 * e + (g_tile[c].load(std::memory_order_relaxed) == 4 ? 1 : 0);
-      m.seg[m.nseg++] = MixedSeg{start, num[c], path, first};
+    for (int j = 0; j < nseg; ++j) {
+      const int c = cls[j];
+      m.seg[m.nseg++] = MixedSeg{start, num[c], path[j], first};
       for (int i = 0; i < num[c]; ++i) m.d[first + i] = host[off[c] + i];
-      start += num[c] * path_groups(path);
+      start += num[c] * path_groups(path[j]);
       first += num[c];
     }
-    if (amax) {
+    if (amax && !parts) {
       hipLaunchKernelGGL(amax_zero_mixed, dim3(1), dim3(64), 0, s, m, first, amax);
       HIP_TRY(hipGetLastError());
     }
-    if (f11)
-      hipLaunchKernelGGL(hydro_mixed_arg_kernel<11>, dim3(start), dim3(Lds8::kThreads), 0, s, m,
-                         dt, dx, amax);
+    if (f11 && parts)
+      hipLaunchKernelGGL((hydro_mixed_arg_kernel<11, true>), dim3(start), dim3(Lds8::kThreads), 0, s,
+                         m, dt, dx, amax);
+    else if (f11)
+      hipLaunchKernelGGL((hydro_mixed_arg_kernel<11, false>), dim3(start), dim3(Lds8::kThreads), 0,
+                         s, m, dt, dx, amax);
+    else if (parts)
+      hipLaunchKernelGGL((hydro_mixed_arg_kernel<6, true>), dim3(start), dim3(Lds8::kThreads), 0, s,
+                         m, dt, dx, amax);
     else
-      hipLaunchKernelGGL(hydro_mixed_arg_kernel<6>, dim3(start), dim3(Lds8::kThreads), 0, s, m,
-                         dt, dx, amax);
+      hipLaunchKernelGGL((hydro_mixed_arg_kernel<6, false>), dim3(start), dim3(Lds8::kThreads), 0, s,
+                         m, dt, dx, amax);
     HIP_TRY(hipGetLastError());
     return HYDRO_OK;
   }
   MixedTable m;
   memset(&m, 0, sizeof m);
   int start = 0, most = 0;
-  for (int e = 0; e < kMixedSegs; ++e) {
-    const int c = 2 * e + f;
-    if (!num[c]) continue;
-    const int path = 2 * e + (g_tile[c].load(std::memory_order_relaxed) == 4 ? 1 : 0);
+  for (int j = 0; j < nseg; ++j) {
+    const int c = cls[j];
     m.table[m.nseg] = table + off[c];
-    m.seg[m.nseg++] = MixedSeg{start, num[c], path, 0};
+    m.seg[m.nseg++] = MixedSeg{start, num[c], path[j], 0};
     most = num[c] > most ? num[c] : most;
     // segments start at multiples of 8: a sub-grid's work-groups stay on one XCD
-    start += grid_for(num[c], path_groups(path));
+    start += grid_for(num[c], path_groups(path[j]));
     start = (start + 7) / 8 * 8;
   }
-  if (amax) {
+  if (amax && !parts) {
     hipLaunchKernelGGL(amax_zero_mixed_table, dim3((most + 255) / 256), dim3(256), 0, s, m, amax);
     HIP_TRY(hipGetLastError());
   }
-  if (f11)
-    hipLaunchKernelGGL(hydro_mixed_kernel<11>, dim3(start), dim3(Lds8::kThreads), 0, s, m, dt, dx,
-                       amax);
+  if (f11 && parts)
+    hipLaunchKernelGGL((hydro_mixed_kernel<11, true>), dim3(start), dim3(Lds8::kThreads), 0, s, m,
+                       dt, dx, amax);
+  else if (f11)
+    hipLaunchKernelGGL((hydro_mixed_kernel<11, false>), dim3(start), dim3(Lds8::kThreads), 0, s, m,
+                       dt, dx, amax);
+  else if (parts)
+    hipLaunchKernelGGL((hydro_mixed_kernel<6, true>), dim3(start), dim3(Lds8::kThreads), 0, s, m,
+                       dt, dx, amax);
   else
-    hipLaunchKernelGGL(hydro_mixed_kernel<6>, dim3(start), dim3(Lds8::kThreads), 0, s, m, dt, dx,
-                       amax);
+    hipLaunchKernelGGL((hydro_mixed_kernel<6, false>), dim3(start), dim3(Lds8::kThreads), 0, s, m,
+                       dt, dx, amax);
   HIP_TRY(hipGetLastError());
   return HYDRO_OK;
 }
 
 int validate_batch(const hydro_subgrid_t* sg, int32_t count, double dt, double dx) {
   return validate(sg, count, dt, dx);
-}
-int launch_class(int cls, const DevDesc* table, int n, double dt, double dx, double* amax,
-                 hipStream_t s) {
-  return dispatch_table(cls, table, n, dt, dx, amax, s);
-}
-
-bool class_single_block(int cls) {
-  // one work-group per sub-grid: 8^3 sub-grids with the 8^3 tile
-  return (cls == 0 || cls == 1) && g_tile[cls].load(std::memory_order_relaxed) == 8;
-}
-
-int launch_class_args(int cls, const DevDesc* host, int n, double dt, double dx, double* amax,
-                      hipStream_t s) {
-  if (n > hydro::kArgDescs) return fail(HYDRO_EINVAL, "%d descriptors exceed the argument form", n);
-  ArgDescs a;
-  for (int i = 0; i < n; ++i) a.d[i] = host[i];
-  return dispatch_args(cls, a, n, dt, dx, amax, s);
 }
 }  // namespace api
 }  // namespace hydro

@@ -58,6 +58,13 @@ struct DevDesc {
 // Descriptors carried by value in the kernel arguments (small batches and
 // the one-launch-per-sub-grid baseline).
 constexpr int kArgDescs = 8;
+
+// Per-work-group amax partials (the aggregator's launches): work-group b of
+// the sub-grid with descriptor index i stores its maximum, with a plain
+// store, at amax_out[i * kAmaxParts + b]; the reader takes the maximum of
+// the first (work-groups per sub-grid) entries.  16 = the most work-groups
+// of one sub-grid (16^3 with 4^3 blocks).
+constexpr int kAmaxParts = 16;
 struct ArgDescs {
   DevDesc d[kArgDescs];
 };

@@ -267,10 +267,12 @@ __device__ __forceinline__ void recon_at(Recon<K>& rc, const double (&q)[K],
 // computed but not written).  MULTI: several blocks share the parent's amax
 // slot (combined with an atomic max of the bit pattern, which orders like the
 // values for non-negative doubles; the slot is zeroed before the launch).
-template <int F, int MP, bool MULTI>
+// PARTS: the block stores its own maximum instead, at partial `part` of the
+// parent's slot (kAmaxParts per sub-grid), with a plain store.
+template <int F, int MP, bool MULTI, bool PARTS = false>
 __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int oy, int oz,
                                           int lox, int loy, int loz, double dt, double dx,
-                                          double* __restrict__ amax_out) {
+                                          double* __restrict__ amax_out, int part = 0) {
   constexpr int M = Lds8::M;
   constexpr int N = Lds8::N;
   constexpr long FS = Frame<MP>::FS;
@@ -467,7 +469,9 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int
     __syncthreads();
     if (t == 0) {
       const double m = fmax(fmax(red[0], red[1]), red[2]);
-      if (MULTI)
+      if constexpr (PARTS)
+        amax_out[(long)d.index * kAmaxParts + part] = m;
+      else if (MULTI)
         atomicMax(reinterpret_cast<unsigned long long*>(&amax_out[d.index]),
                   (unsigned long long)__double_as_longlong(m));
       else

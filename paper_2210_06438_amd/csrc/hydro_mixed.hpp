@@ -58,32 +58,34 @@ struct MixedArgs {
   int nseg;
 };
 
-template <int F, int MP>
+template <int F, int MP, bool PARTS>
 __device__ __forceinline__ void lds8_block(const DevDesc& d, int b, double dt, double dx,
                                            double* __restrict__ amax_out) {
   constexpr int B = Blocks<MP>::kPerSubgrid;
   int org, ox, oy, oz, lox, loy, loz;
   Blocks<MP>::geo(b, org, ox, oy, oz, lox, loy, loz);
-  lds8_step<F, MP, (B > 1)>(d, org, ox, oy, oz, lox, loy, loz, dt, dx, amax_out);
+  lds8_step<F, MP, (B > 1), PARTS>(d, org, ox, oy, oz, lox, loy, loz, dt, dx, amax_out, b);
 }
 
-// Work-group `b` of sub-grid `d` on tile path PATH.
-template <int F, int PATH>
+// Work-group `b` of sub-grid `d` on tile path PATH.  PARTS: amax as
+// per-work-group partials (kAmaxParts per sub-grid, plain stores), else
+// combined in the sub-grid's slot as the class kernels do.
+template <int F, int PATH, bool PARTS>
 __device__ __forceinline__ void run_path(const DevDesc& d, int b, double dt, double dx,
                                          double* __restrict__ amax_out) {
-  if constexpr (PATH == kP8T8) lds8_block<F, 14>(d, b, dt, dx, amax_out);
-  if constexpr (PATH == kP8T4) q4_step<F, 14>(d, b, dt, dx, amax_out);
-  if constexpr (PATH == kP12T8) lds8_block<F, 18>(d, b, dt, dx, amax_out);
-  if constexpr (PATH == kP12T4) q4_step<F, 18>(d, b, dt, dx, amax_out);
-  if constexpr (PATH == kP16T8) lds8_block<F, 22>(d, b, dt, dx, amax_out);
-  if constexpr (PATH == kP16T4) q4_step<F, 22>(d, b, dt, dx, amax_out);
+  if constexpr (PATH == kP8T8) lds8_block<F, 14, PARTS>(d, b, dt, dx, amax_out);
+  if constexpr (PATH == kP8T4) q4_step<F, 14, PARTS>(d, b, dt, dx, amax_out);
+  if constexpr (PATH == kP12T8) lds8_block<F, 18, PARTS>(d, b, dt, dx, amax_out);
+  if constexpr (PATH == kP12T4) q4_step<F, 18, PARTS>(d, b, dt, dx, amax_out);
+  if constexpr (PATH == kP16T8) lds8_block<F, 22, PARTS>(d, b, dt, dx, amax_out);
+  if constexpr (PATH == kP16T4) q4_step<F, 22, PARTS>(d, b, dt, dx, amax_out);
 }
 
 // Work-group lw of a table segment: the mapping of the class kernels, with
 // the path's work-groups per sub-grid a compile-time constant (the
 // descriptor index then stays scalar and the descriptor in scalar
 // registers).
-template <int F, int PATH>
+template <int F, int PATH, bool PARTS>
 __device__ __forceinline__ void table_path(const DevDesc* __restrict__ table, int count, int lw,
                                            double dt, double dx, double* __restrict__ amax_out) {
   constexpr int B = path_groups(PATH);
@@ -91,15 +93,15 @@ __device__ __forceinline__ void table_path(const DevDesc* __restrict__ table, in
   const int b = B == 1 ? 0 : (lw >> 3) % B;
   if (s >= count) return;
   const DevDesc d = table[s];
-  run_path<F, PATH>(d, b, dt, dx, amax_out);
+  run_path<F, PATH, PARTS>(d, b, dt, dx, amax_out);
 }
 
-template <int F, int PATH>
+template <int F, int PATH, bool PARTS>
 __device__ __forceinline__ void arg_path(const MixedArgs& m, int first, int lw, double dt,
                                          double dx, double* __restrict__ amax_out) {
   constexpr int B = path_groups(PATH);
   const DevDesc d = m.d[first + lw / B];
-  run_path<F, PATH>(d, lw % B, dt, dx, amax_out);
+  run_path<F, PATH, PARTS>(d, lw % B, dt, dx, amax_out);
 }
 
 // Segment of work-group w: the last segment that starts at or before it.
@@ -113,7 +115,7 @@ __device__ __forceinline__ int mixed_segment(const MixedSeg (&seg)[kMixedSegs], 
 // Table form (a segment of more than kArgDescs sub-grids).  Within a segment
 // the work-groups of a sub-grid have indices equal modulo 8 (segments start
 // at multiples of 8), as in the class kernels.
-template <int F>
+template <int F, bool PARTS>
 __global__ void __launch_bounds__(Lds8::kThreads, 2)
     hydro_mixed_kernel(MixedTable m, double dt, double dx, double* __restrict__ amax_out) {
   const int w = blockIdx.x;
@@ -122,18 +124,18 @@ __global__ void __launch_bounds__(Lds8::kThreads, 2)
   const DevDesc* table = m.table[j];
   const int lw = w - sg.start;
   switch (sg.path) {
-    case kP8T8: table_path<F, kP8T8>(table, sg.count, lw, dt, dx, amax_out); break;
-    case kP8T4: table_path<F, kP8T4>(table, sg.count, lw, dt, dx, amax_out); break;
-    case kP12T8: table_path<F, kP12T8>(table, sg.count, lw, dt, dx, amax_out); break;
-    case kP12T4: table_path<F, kP12T4>(table, sg.count, lw, dt, dx, amax_out); break;
-    case kP16T8: table_path<F, kP16T8>(table, sg.count, lw, dt, dx, amax_out); break;
-    default: table_path<F, kP16T4>(table, sg.count, lw, dt, dx, amax_out); break;
+    case kP8T8: table_path<F, kP8T8, PARTS>(table, sg.count, lw, dt, dx, amax_out); break;
+    case kP8T4: table_path<F, kP8T4, PARTS>(table, sg.count, lw, dt, dx, amax_out); break;
+    case kP12T8: table_path<F, kP12T8, PARTS>(table, sg.count, lw, dt, dx, amax_out); break;
+    case kP12T4: table_path<F, kP12T4, PARTS>(table, sg.count, lw, dt, dx, amax_out); break;
+    case kP16T8: table_path<F, kP16T8, PARTS>(table, sg.count, lw, dt, dx, amax_out); break;
+    default: table_path<F, kP16T4, PARTS>(table, sg.count, lw, dt, dx, amax_out); break;
   }
 }
 
 // Argument form: segment j holds seg[j].count * path_groups work-groups,
 // sub-grid-major.
-template <int F>
+template <int F, bool PARTS>
 __global__ void __launch_bounds__(Lds8::kThreads, 2)
     hydro_mixed_arg_kernel(MixedArgs m, double dt, double dx, double* __restrict__ amax_out) {
   const int w = blockIdx.x;
@@ -141,12 +143,12 @@ __global__ void __launch_bounds__(Lds8::kThreads, 2)
   const MixedSeg sg = m.seg[j];
   const int lw = w - sg.start;
   switch (sg.path) {
-    case kP8T8: arg_path<F, kP8T8>(m, sg.first, lw, dt, dx, amax_out); break;
-    case kP8T4: arg_path<F, kP8T4>(m, sg.first, lw, dt, dx, amax_out); break;
-    case kP12T8: arg_path<F, kP12T8>(m, sg.first, lw, dt, dx, amax_out); break;
-    case kP12T4: arg_path<F, kP12T4>(m, sg.first, lw, dt, dx, amax_out); break;
-    case kP16T8: arg_path<F, kP16T8>(m, sg.first, lw, dt, dx, amax_out); break;
-    default: arg_path<F, kP16T4>(m, sg.first, lw, dt, dx, amax_out); break;
+    case kP8T8: arg_path<F, kP8T8, PARTS>(m, sg.first, lw, dt, dx, amax_out); break;
+    case kP8T4: arg_path<F, kP8T4, PARTS>(m, sg.first, lw, dt, dx, amax_out); break;
+    case kP12T8: arg_path<F, kP12T8, PARTS>(m, sg.first, lw, dt, dx, amax_out); break;
+    case kP12T4: arg_path<F, kP12T4, PARTS>(m, sg.first, lw, dt, dx, amax_out); break;
+    case kP16T8: arg_path<F, kP16T8, PARTS>(m, sg.first, lw, dt, dx, amax_out); break;
+    default: arg_path<F, kP16T4, PARTS>(m, sg.first, lw, dt, dx, amax_out); break;
   }
 }
 

@@ -116,7 +116,9 @@ __device__ __forceinline__ void q4_load_ghosts(const double* __restrict__ src, i
   }
 }
 
-template <int F, int MP>
+// PARTS: the work-group stores its maximum at partial `group` of the
+// sub-grid's slot (kAmaxParts per sub-grid) instead of the atomic max.
+template <int F, int MP, bool PARTS = false>
 __device__ __forceinline__ void q4_step(const DevDesc& d, int group, double dt, double dx,
                                         double* __restrict__ amax_out) {
   constexpr int M = Q4::M;
@@ -289,8 +291,11 @@ __device__ __forceinline__ void q4_step(const DevDesc& d, int group, double dt, 
     __syncthreads();
     if (t == 0) {
       const double m = fmax(fmax(red[0], red[1]), red[2]);
-      atomicMax(reinterpret_cast<unsigned long long*>(&amax_out[d.index]),
-                (unsigned long long)__double_as_longlong(m));
+      if constexpr (PARTS)
+        amax_out[(long)d.index * kAmaxParts + group] = m;
+      else
+        atomicMax(reinterpret_cast<unsigned long long*>(&amax_out[d.index]),
+                  (unsigned long long)__double_as_longlong(m));
     }
   }
 }

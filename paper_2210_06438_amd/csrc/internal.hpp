@@ -21,19 +21,6 @@ constexpr int kNumClasses = 6;
 // Argument checks of hydro_step (0 or HYDRO_EINVAL).
 int validate_batch(const hydro_subgrid_t* sg, int32_t count, double dt, double dx);
 
-// One aggregated launch of `n` sub-grids of class `cls` whose descriptors are
-// at `table` (device memory), on stream `s`.
-int launch_class(int cls, const DevDesc* table, int n, double dt, double dx, double* amax,
-                 hipStream_t s);
-// True when class `cls` steps each sub-grid with one work-group, which then
-// writes its amax slot with a plain store (no zeroing, no atomics).
-bool class_single_block(int cls);
-
-// The same with at most kArgDescs descriptors read from host memory and
-// passed in the kernel arguments (no descriptor copy on the stream).
-int launch_class_args(int cls, const DevDesc* host, int n, double dt, double dx, double* amax,
-                      hipStream_t s);
-
 // True when a batch with per-class counts num[] can be one launch_mixed:
 // at least two classes present, all of one field count.
 bool mixed_eligible(const int* num);
@@ -42,10 +29,14 @@ bool mixed_eligible(const int* num);
 // num[c] sub-grids whose descriptors start at index off[c], n in all.  When
 // `host` is given and every class has at most kArgDescs they are read from
 // `host` into the kernel arguments; otherwise from the device table `table`
-// (table + off[c] for class c).  amax slots (if amax is not NULL) are
-// zeroed first, on the same stream.
+// (table + off[c] for class c).  amax: without `parts`, one slot per
+// sub-grid, zeroed first on the same stream; with `parts` (one class or
+// more), kAmaxParts partials per sub-grid written with plain stores and
+// nothing zeroed, and groups[c] receives the work-groups per sub-grid of
+// class c (the partials to read).
 int launch_mixed(const int* num, const int* off, const DevDesc* host, const DevDesc* table,
-                 int n, double dt, double dx, double* amax, hipStream_t s);
+                 int n, double dt, double dx, double* amax, hipStream_t s, bool parts = false,
+                 int* groups = nullptr);
 
 }  // namespace api
 }  // namespace hydro
