@@ -262,7 +262,7 @@ def main():
     ap.add_argument("--uneven-steps", type=int, default=100)
     ap.add_argument("--uneven-each", type=int, default=1,
                     help="1: also time the uneven batch with one launch per sub-grid")
-    ap.add_argument("--serve-rates", type=float, nargs="*", default=[20000.0, 200000.0, 2000000.0])
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=[20000.0, 200000.0, 2000000.0, 5000000.0])
     ap.add_argument("--per-task-max-rate", type=float, default=200000.0,
                     help="skip the per-task-launch baseline above this rate (it saturates "
                          "near 60k tasks/s)")
