@@ -191,12 +191,14 @@ def main(argv=None):
                     help="also launch whenever a stream is idle (off: width and timeout only)")
     ap.add_argument("--repeats", type=int, default=1,
                     help="independent arrival sequences per point (median p99 recorded)")
+    ap.add_argument("--rates", type=float, nargs="*", default=RATES,
+                    help="offered task rates (tasks/s)")
     a = ap.parse_args(argv)
     t0 = time.time()
-    recs = sweep(seconds=a.seconds, streams=a.streams, flush_when_idle=a.idle_flush,
+    recs = sweep(rates=a.rates, seconds=a.seconds, streams=a.streams, flush_when_idle=a.idle_flush,
                  repeats=a.repeats, log=lambda m: print(m, flush=True))
     with open(a.out, "w") as f:
-        json.dump({"widths": WIDTHS, "edges": EDGES, "fields": FIELDS, "rates": RATES,
+        json.dump({"widths": WIDTHS, "edges": EDGES, "fields": FIELDS, "rates": list(a.rates),
                    "seconds": a.seconds, "streams": a.streams, "timeout_us": 50.0,
                    "flush_when_idle": a.idle_flush, "slab_budget_mb": 64.0,
                    "repeats": a.repeats,
