@@ -154,13 +154,15 @@ def learned_leg(args, dev):
     out = {"splits": args.learned_splits, "epochs": 2000, "features": 5,
            "overload_clip_us": learned.OVERLOAD_US,
            "exhaustive_runs_per_condition": len(learned.WIDTHS), "model_runs_per_condition": 0}
-    for name in ("timeout", "idle_r3"):
+    policies = {"timeout": "launch on width or 50 us timeout",
+                "idle_r3": "launch on width, 50 us timeout or idle stream",
+                "timeout_to2m": "launch on width or 50 us timeout; current runtime, rates to 2M/s"}
+    for name in policies:
         recs = learned.load_sweep(name)
         t0 = time.time()
         cv = learned.cross_validate(recs, splits=range(args.learned_splits), device=dev)
         sec = time.time() - t0
-        out[name] = {"policy": ("launch on width or 50 us timeout" if name == "timeout"
-                                else "launch on width, 50 us timeout or idle stream"),
+        out[name] = {"policy": policies[name],
                      "model_mean_regret": round(cv["mlp_mean_regret"], 4),
                      "static_mean_regret": round(cv["static_mean_regret"], 4),
                      "model_median_regret": round(cv["mlp_median_regret"], 4),
@@ -172,7 +174,9 @@ def learned_leg(args, dev):
             f"{cv['mlp_median_regret']:.3f} vs best static {cv['static_mean_regret']:.3f} / "
             f"{cv['static_median_regret']:.3f}, wins {cv['mlp_wins']}/{args.learned_splits}, "
             f"{sec / args.learned_splits:.2f} s per model")
-    model = learned.WidthModel(device=dev).fit(learned.load_sweep("timeout"))
+    # the serving policy's width comes from the sweep that covers its rates
+    model = learned.WidthModel(device=dev).fit(learned.load_sweep("timeout_to2m"))
+    out["serving_model_sweep"] = "timeout_to2m"
     return out, model
 
 

@@ -4,18 +4,22 @@ on timings that the width sweeps produce, used to pick the width of a
 serving condition without sweeping it.
 
 Features of (n, nfields, rate, width): log2 width, n/16, nfields/11,
-log10 rate, log2 bytes per task.  Target: log p99 latency, standardised,
-with p99 clipped at OVERLOAD_US first: above it the width cannot keep up
-with the arrival rate, the queue grows for as long as the run lasts, and the
-exact figure measures the run's length rather than the width, while its
-magnitude (up to seconds) would otherwise dominate the squared error.
+log10 rate, log2 bytes per task.  Target (target()): log p99 latency,
+standardised, with p99 clipped at OVERLOAD_US first: above it the width
+cannot keep up with the arrival rate, the queue grows for as long as the run
+lasts, and the exact figure measures the run's length rather than the
+width, while its magnitude (up to seconds) would otherwise dominate the
+squared error; plus the throughput deficit log(rate / throughput), which
+still ranks the widths that cannot keep up.
 The chosen width of a condition is the argmin of the prediction over the
 candidate widths; the exhaustive tuner (tune.py) is its fallback and judge.
 
-Sweeps stored under data/ (420 records each, made by tune.py on one MI355X):
-  width_sweep_timeout.json  launch on width or 50 us timeout only
-  width_sweep_idle.json     also launch whenever a stream is idle
-  width_sweep_idle_r3.json  the same, median p99 of 3 arrival sequences per point
+Sweeps stored under data/ (made by tune.py on one MI355X):
+  width_sweep_timeout.json       launch on width or 50 us timeout only (420 records)
+  width_sweep_idle.json          also launch whenever a stream is idle (420)
+  width_sweep_idle_r3.json       the same, median p99 of 3 arrival sequences per point (420)
+  width_sweep_timeout_to2m.json  width or timeout, the runtime with multi-class launches and
+                                 amax partials, rates up to 2M tasks/s (600)
 """
 from __future__ import annotations
 
@@ -31,6 +35,22 @@ from .tune import WIDTHS, best_width, task_bytes
 
 NPARAM = 4609
 OVERLOAD_US = 2000.0
+# shortfalls of the measured throughput below the offered rate up to this
+# (log) fraction are the finite run's drain, not a width that cannot keep up
+DRAIN_SLACK = 0.1
+
+
+def target(records, overload_us=OVERLOAD_US):
+    """Learning target of each record: log p99 with p99 clipped at
+    overload_us, plus the throughput deficit log(rate / throughput) beyond
+    DRAIN_SLACK.  Past saturation the clipped p99 is the same for every
+    width; the deficit still ranks them (how far each falls behind the
+    offered rate), and it is zero wherever the width keeps up."""
+    p99 = np.array([r["p99_us"] for r in records], dtype=np.float64)
+    rate = np.array([r["rate"] for r in records], dtype=np.float64)
+    tput = np.array([r["throughput"] for r in records], dtype=np.float64)
+    deficit = np.maximum(np.log(rate / np.maximum(tput, 1e-9)) - DRAIN_SLACK, 0.0)
+    return np.log(np.minimum(p99, overload_us)) + deficit
 DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
 
 
@@ -187,7 +207,7 @@ class WidthModel:
     def fit(self, records, epochs=2000, lr=1e-3):
         X = features([r["n"] for r in records], [r["nfields"] for r in records],
                      [r["rate"] for r in records], [r["width"] for r in records])
-        y = np.log(np.minimum([r["p99_us"] for r in records], self.overload_us))
+        y = target(records, self.overload_us)
         self.xm, self.xs = X.mean(0), X.std(0) + 1e-12
         self.ym, self.ys = y.mean(), y.std() + 1e-12
         self.mlp = MLP(seed=self.seed, device=self.device)

@@ -14,7 +14,7 @@ def _choose(records, train, test, epochs=2000, lr=1e-3):
     rows = learned.in_groups(records, train)
     X = learned.features([r["n"] for r in rows], [r["nfields"] for r in rows],
                          [r["rate"] for r in rows], [r["width"] for r in rows])
-    y = np.log(np.minimum([r["p99_us"] for r in rows], learned.OVERLOAD_US))
+    y = learned.target(rows)
     xm, xs = X.mean(0), X.std(0) + 1e-12
     ym, ys = y.mean(), y.std() + 1e-12
     p = M.init(0)
