@@ -55,3 +55,17 @@ def test_recipe_beats_best_static_width():
         mlp.append(np.mean([learned.regret(recs, g, pick[g]) for g in test]))
         static.append(np.mean([learned.regret(recs, g, sw) for g in test]))
     assert np.mean(mlp) < 0.5 * np.mean(static), (mlp, static)
+
+
+def test_target_ranks_widths_past_saturation():
+    """The learning target is log(min(p99, 2 ms)) where a width keeps up
+    (throughput within the drain slack of the rate), and grows with the
+    throughput deficit where it does not, so two saturated widths with the
+    same clipped p99 still differ by how far each falls behind."""
+    rec = lambda p99, tput: {"p99_us": p99, "rate": 1e6, "throughput": tput}
+    t = learned.target([rec(80.0, 0.99e6), rec(80.0, 0.95e6),
+                        rec(5e6, 2e5), rec(9e6, 5e5), rec(1e3, 1e6)])
+    assert t[0] == np.log(80.0) and t[1] == np.log(80.0)        # drain, not deficit
+    assert np.isclose(t[2], np.log(2000.0) + np.log(5.0) - learned.DRAIN_SLACK)
+    assert np.isclose(t[3], np.log(2000.0) + np.log(2.0) - learned.DRAIN_SLACK)
+    assert t[2] > t[3] > np.log(2000.0) > t[4] == np.log(1e3)
