@@ -2,12 +2,12 @@
 // continuous-batching serving loop built on it.
 //
 // The aggregator (paper Section V-D, strategy 3) holds sub-grid tasks while
-// its streams are busy and launches them as one batch (one kernel per shape
-// class) by the rules of agg_policy.hpp.  Every resource a batch needs -- a
-// pinned descriptor table, a device descriptor table, a device amax array and
-// its pinned copy, an event -- comes from slots allocated at create time, as
-// are the streams: nothing is allocated or created on the submit path
-// (Section V-C).
+// its streams are busy and launches them as one batch (one multi-class
+// kernel per field count) by the rules of agg_policy.hpp.  Every resource a
+// batch needs -- a pinned descriptor table, a device descriptor table, a
+// pinned array of amax partials, a pinned completion word -- comes from
+// slots allocated at create time, as are the streams: nothing is allocated
+// or created on the submit path (Section V-C).
 #include <hip/hip_runtime.h>
 
 #include <string.h>
