@@ -417,29 +417,29 @@ int launch_mixed(const int* num, const int* off, const DevDesc* host, const DevD
   int start = 0, most = 0;
   for (int j = 0; j < nseg; ++j) {
     const int c = cls[j];
-    m.table[m.nseg] = table + off[c];
-    m.seg[m.nseg++] = MixedSeg{start, num[c], path[j], 0};
+    m.seg[m.nseg++] = MixedSeg{start, num[c], path[j], off[c]};
     most = num[c] > most ? num[c] : most;
     // segments start at multiples of 8: a sub-grid's work-groups stay on one XCD
     start += grid_for(num[c], path_groups(path[j]));
     start = (start + 7) / 8 * 8;
   }
   if (amax && !parts) {
-    hipLaunchKernelGGL(amax_zero_mixed_table, dim3((most + 255) / 256), dim3(256), 0, s, m, amax);
+    hipLaunchKernelGGL(amax_zero_mixed_table, dim3((most + 255) / 256), dim3(256), 0, s, table, m,
+                       amax);
     HIP_TRY(hipGetLastError());
   }
   if (f11 && parts)
-    hipLaunchKernelGGL((hydro_mixed_kernel<11, true>), dim3(start), dim3(Lds8::kThreads), 0, s, m,
-                       dt, dx, amax);
+    hipLaunchKernelGGL((hydro_mixed_kernel<11, true>), dim3(start), dim3(Lds8::kThreads), 0, s,
+                       table, m, dt, dx, amax);
   else if (f11)
-    hipLaunchKernelGGL((hydro_mixed_kernel<11, false>), dim3(start), dim3(Lds8::kThreads), 0, s, m,
-                       dt, dx, amax);
+    hipLaunchKernelGGL((hydro_mixed_kernel<11, false>), dim3(start), dim3(Lds8::kThreads), 0, s,
+                       table, m, dt, dx, amax);
   else if (parts)
-    hipLaunchKernelGGL((hydro_mixed_kernel<6, true>), dim3(start), dim3(Lds8::kThreads), 0, s, m,
-                       dt, dx, amax);
+    hipLaunchKernelGGL((hydro_mixed_kernel<6, true>), dim3(start), dim3(Lds8::kThreads), 0, s,
+                       table, m, dt, dx, amax);
   else
-    hipLaunchKernelGGL((hydro_mixed_kernel<6, false>), dim3(start), dim3(Lds8::kThreads), 0, s, m,
-                       dt, dx, amax);
+    hipLaunchKernelGGL((hydro_mixed_kernel<6, false>), dim3(start), dim3(Lds8::kThreads), 0, s,
+                       table, m, dt, dx, amax);
   HIP_TRY(hipGetLastError());
   return HYDRO_OK;
 }

@@ -37,21 +37,22 @@ struct MixedSeg {
   int start;   // first work-group of the segment in the grid
   int count;   // sub-grids
   int path;    // MixedPath
-  int first;   // first descriptor of the segment (argument form)
+  int first;   // first descriptor of the segment
 };
 
-// Descriptors in device memory, one table per segment.
+// Segments of a batch whose descriptors are in device memory: one table,
+// passed to the kernel as a separate restrict-qualified argument (the
+// compiler then treats its loads as invariant and keeps the descriptor out
+// of the registers that the step needs -- with the table pointers inside
+// this struct instead, the kernel spilled 52-60 bytes per lane).
 struct MixedTable {
-  const DevDesc* table[kMixedSegs];
   MixedSeg seg[kMixedSegs];
   int nseg;
 };
 
 // Descriptors in the kernel arguments: at most kArgDescs per segment (576
 // bytes of arguments; a larger block -- 64 descriptors, 1.5 KB -- made each
-// launch measurably slower).  Every default path of this form compiles
-// without register spills; the table form below spills a few registers per
-// lane once it holds two paths or more.
+// launch measurably slower).
 struct MixedArgs {
   DevDesc d[kMixedSegs * kArgDescs];
   MixedSeg seg[kMixedSegs];
@@ -86,13 +87,14 @@ __device__ __forceinline__ void run_path(const DevDesc& d, int b, double dt, dou
 // descriptor index then stays scalar and the descriptor in scalar
 // registers).
 template <int F, int PATH, bool PARTS>
-__device__ __forceinline__ void table_path(const DevDesc* __restrict__ table, int count, int lw,
-                                           double dt, double dx, double* __restrict__ amax_out) {
+__device__ __forceinline__ void table_path(const DevDesc* __restrict__ table, int first, int count,
+                                           int lw, double dt, double dx,
+                                           double* __restrict__ amax_out) {
   constexpr int B = path_groups(PATH);
   const int s = B == 1 ? lw : (lw / (8 * B)) * 8 + (lw & 7);
   const int b = B == 1 ? 0 : (lw >> 3) % B;
   if (s >= count) return;
-  const DevDesc d = table[s];
+  const DevDesc d = table[first + s];
   run_path<F, PATH, PARTS>(d, b, dt, dx, amax_out);
 }
 
@@ -117,19 +119,19 @@ __device__ __forceinline__ int mixed_segment(const MixedSeg (&seg)[kMixedSegs], 
 // at multiples of 8), as in the class kernels.
 template <int F, bool PARTS>
 __global__ void __launch_bounds__(Lds8::kThreads, 2)
-    hydro_mixed_kernel(MixedTable m, double dt, double dx, double* __restrict__ amax_out) {
+    hydro_mixed_kernel(const DevDesc* __restrict__ table, MixedTable m, double dt, double dx,
+                       double* __restrict__ amax_out) {
   const int w = blockIdx.x;
   const int j = mixed_segment(m.seg, m.nseg, w);
   const MixedSeg sg = m.seg[j];
-  const DevDesc* table = m.table[j];
   const int lw = w - sg.start;
   switch (sg.path) {
-    case kP8T8: table_path<F, kP8T8, PARTS>(table, sg.count, lw, dt, dx, amax_out); break;
-    case kP8T4: table_path<F, kP8T4, PARTS>(table, sg.count, lw, dt, dx, amax_out); break;
-    case kP12T8: table_path<F, kP12T8, PARTS>(table, sg.count, lw, dt, dx, amax_out); break;
-    case kP12T4: table_path<F, kP12T4, PARTS>(table, sg.count, lw, dt, dx, amax_out); break;
-    case kP16T8: table_path<F, kP16T8, PARTS>(table, sg.count, lw, dt, dx, amax_out); break;
-    default: table_path<F, kP16T4, PARTS>(table, sg.count, lw, dt, dx, amax_out); break;
+    case kP8T8: table_path<F, kP8T8, PARTS>(table, sg.first, sg.count, lw, dt, dx, amax_out); break;
+    case kP8T4: table_path<F, kP8T4, PARTS>(table, sg.first, sg.count, lw, dt, dx, amax_out); break;
+    case kP12T8: table_path<F, kP12T8, PARTS>(table, sg.first, sg.count, lw, dt, dx, amax_out); break;
+    case kP12T4: table_path<F, kP12T4, PARTS>(table, sg.first, sg.count, lw, dt, dx, amax_out); break;
+    case kP16T8: table_path<F, kP16T8, PARTS>(table, sg.first, sg.count, lw, dt, dx, amax_out); break;
+    default: table_path<F, kP16T4, PARTS>(table, sg.first, sg.count, lw, dt, dx, amax_out); break;
   }
 }
 
@@ -154,10 +156,11 @@ __global__ void __launch_bounds__(Lds8::kThreads, 2)
 
 // amax slots of a table-form batch set to zero before the launch: lane i of
 // the grid clears slot i of every segment that has one.
-__global__ void amax_zero_mixed_table(MixedTable m, double* __restrict__ amax_out) {
+__global__ void amax_zero_mixed_table(const DevDesc* __restrict__ table, MixedTable m,
+                                      double* __restrict__ amax_out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   for (int j = 0; j < m.nseg; ++j)
-    if (i < m.seg[j].count) amax_out[m.table[j][i].index] = 0.0;
+    if (i < m.seg[j].count) amax_out[table[m.seg[j].first + i].index] = 0.0;
 }
 
 // amax slots of an argument-form batch set to zero before the launch (one
