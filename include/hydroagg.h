@@ -86,9 +86,8 @@ int hydro_get_tile(int32_t n, int32_t nfields, int32_t *tile);
 /*
  * hydro_step -- one stage for `count` sub-grids (paper Section IV-B), as one
  * aggregated launch per (n, nfields) class present in the batch; a batch of
- * several classes of one field count whose classes are each below 1024
- * work-groups is ONE launch in which the classes run side by side (results
- * bitwise those of the per-class launches).
+ * several classes of one field count is ONE launch in which the classes run
+ * side by side (results bitwise those of the per-class launches).
  *   sg       host array of `count` descriptors (copied before return).
  *   dt       time-step, >= 0 and finite.  dt = 0 leaves the interior equal to
  *            u_in and still produces amax (used to pick the Courant dt).
@@ -127,10 +126,11 @@ int hydro_step_each(const hydro_subgrid_t *sg, int32_t count, double dt,
  * the step path).  hydro_plan_step then only launches kernels, grouped as
  * in hydro_step, with its results and errors.
  * hydro_plan_launch_graph runs the same launches as ONE hipGraph launch on
- * `stream`; classes of at least 1024 work-groups become independent
- * branches of the graph and run concurrently, smaller ones run in sequence
- * (results are those of hydro_plan_step, bit for bit); the graph is
- * captured on private streams at first use and
+ * `stream`, the classes of one field count as one launch; with two field
+ * counts, classes of at least 1024 work-groups become independent branches
+ * of the graph and run concurrently (results are those of
+ * hydro_plan_step, bit for bit); the graph is captured on private streams
+ * at first use and
  * captured again whenever dt, dx, amax_dev or a class's tile change.  A plan may be used
  * from one host thread at a time; hydro_plan_destroy waits for its work.
  */

@@ -231,11 +231,12 @@ int class_groups(int c, int n) {
   return hydro::grid_for(n, B);
 }
 
-// A class becomes a branch of its own only when its grid is at least two
-// full rounds of resident work-groups (2 per CU on 256 CUs): a branch's
-// fork and join cost the step ~25 us, which only the overlap of large
-// launches (their partly filled last waves) pays back; small classes run in
-// sequence on the capture stream.
+// In a graph of a plan with two field counts, a class becomes a branch of
+// its own only when its grid is at least two full rounds of resident
+// work-groups (2 per CU on 256 CUs): a branch's fork and join cost the step
+// ~25 us, which only the overlap of large launches (their partly filled
+// last waves) pays back; small classes run in sequence on the capture
+// stream (several of one field count as one multi-class launch).
 constexpr int kBranchGroups = 1024;
 
 // One chunk of at most kSlotCap sub-grids starting at batch offset `base`.
@@ -262,14 +263,10 @@ int step_chunk(DeviceState* st, const hydro_subgrid_t* sg, int count, int base,
     }
     return hydro::api::launch_mixed(per_class, off, host, nullptr, count, dt, dx, amax, stream);
   }
-  // A larger one whose classes are all below kBranchGroups work-groups: one
-  // launch from a device table (classes side by side).  Larger classes keep
-  // their own launches: their grids overlap little, and the table form of
-  // the multi-class kernel spills a few registers.
-  bool fuse = hydro::api::mixed_eligible(per_class);
-  for (int c = 0; c < kClasses && fuse; ++c)
-    fuse = !per_class[c] || class_groups(c, per_class[c]) < kBranchGroups;
-  if (fuse) {
+  // A larger one: one launch from a device table (classes side by side; for
+  // large classes this overlaps the partly filled last waves of their
+  // grids, which one launch per class would run one after another).
+  if (hydro::api::mixed_eligible(per_class)) {
     Slot* slot;
     {
       std::lock_guard<std::mutex> lk(st->mu);
@@ -477,12 +474,10 @@ struct hydro_plan {
 namespace {
 
 int plan_launches(hydro_plan* p, double dt, double dx, double* amax, hipStream_t s) {
-  // several classes of one field count, all below kBranchGroups work-groups:
-  // one multi-class launch (as hydro_step does)
-  bool fuse = hydro::api::mixed_eligible(p->num);
-  for (int c = 0; c < kClasses && fuse; ++c)
-    fuse = !p->num[c] || class_groups(c, p->num[c]) < kBranchGroups;
-  if (fuse) return hydro::api::launch_mixed(p->num, p->off, nullptr, p->table, p->count, dt, dx, amax, s);
+  // several classes of one field count: one multi-class launch (as
+  // hydro_step does)
+  if (hydro::api::mixed_eligible(p->num))
+    return hydro::api::launch_mixed(p->num, p->off, nullptr, p->table, p->count, dt, dx, amax, s);
   for (int c = 0; c < kClasses; ++c) {
     if (!p->num[c]) continue;
     int rc = dispatch_table(c, p->table + p->off[c], p->num[c], dt, dx, amax, s);
@@ -501,6 +496,12 @@ int plan_capture_branches(hydro_plan* p, double dt, double dx, double* amax) {
       rc = fail(HYDRO_EHIP, "%s failed: %s", what, hipGetErrorString(e));
     return e == hipSuccess;
   };
+  // several classes of one field count: one multi-class launch, whatever
+  // their sizes (as fast as branches for large classes, without the fork
+  // and join)
+  if (hydro::api::mixed_eligible(p->num))
+    return hydro::api::launch_mixed(p->num, p->off, nullptr, p->table, p->count, dt, dx, amax,
+                                    p->capture);
   bool big[kClasses] = {};
   int nbig = 0;
   for (int c = 0; c < kClasses; ++c)
@@ -535,15 +536,16 @@ int plan_capture_branches(hydro_plan* p, double dt, double dx, double* amax) {
   // the rest on the capture stream: the small classes (below kBranchGroups)
   // as one multi-class launch when they are several of one field count, the
   // others one launch each
-  int small[kClasses] = {0};
-  for (int c = 0; c < kClasses; ++c)
-    if (!done[c] && p->num[c] && !big[c]) small[c] = p->num[c];
-  if (hydro::api::mixed_eligible(small)) {
-    int n = 0;
-    for (int c = 0; c < kClasses; ++c) {
-      n += small[c];
+  for (int f = 0; f < 2; ++f) {
+    int small[kClasses] = {0}, n = 0;
+    for (int c = f; c < kClasses; c += 2)
+      if (!done[c] && p->num[c] && !big[c]) {
+        small[c] = p->num[c];
+        n += small[c];
+      }
+    if (!hydro::api::mixed_eligible(small)) continue;
+    for (int c = f; c < kClasses; c += 2)
       if (small[c]) done[c] = true;
-    }
     if (rc == HYDRO_OK)
       rc = hydro::api::launch_mixed(small, p->off, nullptr, p->table, n, dt, dx, amax, p->capture);
   }
