@@ -235,3 +235,32 @@ def test_aggregator_mixed_batch_table_form(dev, tiles):
     finally:
         for k, t in before.items():
             hydroagg.set_tile(*k, t)
+
+
+def test_aggregator_batch_of_two_field_counts(dev):
+    """One batch holding sub-grids of both field counts and all three edges
+    (one multi-class launch per field count, amax partials of both): every
+    task is bitwise what it is stepped alone."""
+    dt, dx = 0.002, 0.05
+    shapes = [(8, 6, 3), (12, 6, 2), (16, 6, 2), (8, 11, 4), (12, 11, 2), (16, 11, 9)]
+    Us = {(n, nf): workloads.random_smooth(c, n=n, nfields=nf, seed=1600 + n + nf)
+          for n, nf, c in shapes}
+    ins = {k: torch.from_numpy(U).to(dev) for k, U in Us.items()}
+    outs = {k: t.clone() for k, t in ins.items()}
+    descs = {k: hydroagg.subgrids(ins[k], outs[k])[0] for k in Us}
+    print("agg two field counts", flush=True)
+    agg = hydroagg.Aggregator(64, timeout_us=-1.0, n_streams=1, flush_when_idle=False)
+    order = [(k, i) for k in Us for i in range(len(Us[k]))]
+    np.random.default_rng(3).shuffle(order)
+    tickets = [(k, i, agg.submit(descs[k][i], dt, dx)) for k, i in order]
+    agg.flush()
+    got = {(k, i): agg.wait(t) for k, i, t in tickets}
+    st = agg.stats()
+    agg.close()
+    torch.cuda.synchronize()
+    assert st["batches"] == 1 and st["launched"] == len(order)
+    for k, U in Us.items():
+        ref, ref_a = alone(U, dt, dx)
+        O = outs[k].cpu().numpy()
+        for i in range(len(U)):
+            assert np.array_equal(O[i], ref[i]) and got[(k, i)] == ref_a[i], (k, i)
