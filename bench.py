@@ -237,7 +237,9 @@ def serving_leg(args, torch, hydroagg, np, tensors, dt, dx, dev, model=None):
                    "cell_updates_s": round(float(cells_of[task].sum()) / span, 1),
                    "batches": st["agg"]["batches"],
                    "mean_batch": round(n / max(st["agg"]["batches"], 1), 2),
-                   "max_live": st["max_live"]}
+                   "max_live": st["max_live"],
+                   "host_us_per_batch": round(st["launch_host_us"] / max(st["agg"]["batches"], 1), 2),
+                   "launch_share_of_makespan": round(st["launch_host_us"] / max(st["makespan_us"], 1e-9), 3)}
             out["runs"].append(rec)
             log(f"serving {label} at {rate}/s: p50 {rec['p50_us']} us, p99 {rec['p99_us']} us, "
                 f"{rec['throughput_tasks_s']:.0f} tasks/s, mean batch {rec['mean_batch']}")

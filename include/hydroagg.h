@@ -219,6 +219,7 @@ typedef struct {
   double first_admit_us;
   uint64_t max_live;       /* most tasks admitted and not yet completed    */
   uint64_t slab_waits;     /* loop passes where an arrived task had no slab */
+  double launch_host_us;   /* host time in batch launches (runtime calls)  */
 } hydro_serve_stats_t;
 
 int hydro_serve_run(const hydro_serve_config_t *cfg, const hydro_subgrid_t *pool,

@@ -93,7 +93,19 @@ class HipExec {
     return it == live_.end() || finished(it->second);
   }
 
+  // Host time spent in launch() (descriptor packing and the runtime calls).
+  double launch_us() const { return launch_us_; }
+
   int launch(int s, const Task* t, int n, double dt, double dx, uint64_t batch) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int rc = launch_batch(s, t, n, dt, dx, batch);
+    launch_us_ +=
+        std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+  }
+
+ private:
+  int launch_batch(int s, const Task* t, int n, double dt, double dx, uint64_t batch) {
     if (n > cap_) return fail(HYDRO_ENOMEM, "batch of %d exceeds the width %d", n, cap_);
     int k = free_slot();
     if (k < 0) {
@@ -160,6 +172,7 @@ class HipExec {
     return HYDRO_OK;
   }
 
+ public:
   bool done(uint64_t batch) {
     auto r = retired_.find(batch);
     if (r != retired_.end()) return true;
@@ -266,6 +279,7 @@ class HipExec {
   }
 
   int ns_ = 0, created_ = 0, cap_ = 0;
+  double launch_us_ = 0.0;
   hipStream_t streams_[8] = {};
   std::vector<Slot> slots_;
   uint64_t* flags_ = nullptr;   // pinned; flags_[k] = id of the last finished batch of slot k
@@ -558,6 +572,7 @@ extern "C" int hydro_serve_run(const hydro_serve_config_t* cfg, const hydro_subg
     stats->first_admit_us = t_first;
     stats->max_live = max_live;
     stats->slab_waits = slab_waits;
+    stats->launch_host_us = agg->ex.launch_us();
   }
   {
     const int rc2 = hydro_agg_destroy(agg);

@@ -62,7 +62,7 @@ class hydro_serve_config_t(ctypes.Structure):
 class hydro_serve_stats_t(ctypes.Structure):
     _fields_ = [("agg", hydro_agg_stats_t), ("makespan_us", ctypes.c_double),
                 ("first_admit_us", ctypes.c_double), ("max_live", ctypes.c_uint64),
-                ("slab_waits", ctypes.c_uint64)]
+                ("slab_waits", ctypes.c_uint64), ("launch_host_us", ctypes.c_double)]
 
 _lib = None
 
@@ -335,5 +335,5 @@ def serve_run(pool_descs, task_subgrid, arrival_us, *, nfields, dt, dx, slab_are
                                  slabs.ctypes.data if want_slabs else None, ctypes.byref(st)))
     stats = {"agg": st.agg.as_dict(), "makespan_us": st.makespan_us,
              "first_admit_us": st.first_admit_us, "max_live": int(st.max_live),
-             "slab_waits": int(st.slab_waits)}
+             "slab_waits": int(st.slab_waits), "launch_host_us": st.launch_host_us}
     return lat, am, slabs, stats
