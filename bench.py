@@ -144,7 +144,74 @@ def uneven_leg(args, torch, hydroagg, workloads, dev, stream):
             "ms_per_step": round(each_ms, 3), "value": round(cells / (each_ms * 1e-3), 1)},
         "aggregation_speedup": None if each_ms is None else round(each_ms / ms, 2),
     }
-    return res, tensors, dt, dx
+    return res, tensors, dt, dx, groups
+
+
+def _time_oracle(oracle, U, dt, dx, threads, seconds, levels=None, reps=2):
+    """Median wall time of oracle.step over repetitions lasting >= seconds."""
+    times = []
+    t_all = time.time()
+    while len(times) < reps or time.time() - t_all < seconds:
+        t0 = time.time()
+        oracle.step(U, dt, dx, levels=levels, nthreads=threads)
+        times.append(time.time() - t0)
+    return statistics.median(times), len(times), sum(times)
+
+
+def cpu_baseline_leg(args, U, dt, dx, cells, poly):
+    """The CPU oracle timed on the host cores: on all of them over the whole
+    headline batch (the paper's 32-core row, Table III), on one thread over
+    the first --cpu-single-count sub-grids (its 1-core row), and on all cores
+    over the polytrope batch, with the limiter-branch and non-positive-state
+    counters of one sequential pass over it."""
+    import oracle
+    threads = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS", "0") or 0) \
+        or os.cpu_count() or 1
+    count = U.shape[0]
+    n = U.shape[2] - 2 * GHOST
+    log(f"cpu baseline: oracle on the full batch, {threads} threads, >= {args.cpu_seconds:.0f} s")
+    med, reps, wall = _time_oracle(oracle, U, dt, dx, threads, args.cpu_seconds)
+    cpu = {"value": round(cells / med, 1), "unit": "cell-updates/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"the full {count}-sub-grid workload stepped {reps} times "
+                     f"({wall:.1f} s wall, median {med:.3f} s per step), OpenMP over sub-grids"}
+    log(f"cpu baseline {cells / med / 1e6:.2f} M cell-updates/s on {threads} threads")
+    k = min(args.cpu_single_count, count)
+    med1, reps1, wall1 = _time_oracle(oracle, U[:k], dt, dx, 1, args.cpu_single_seconds)
+    c1 = k * n ** 3
+    cpu["single_thread"] = {
+        "value": round(c1 / med1, 1), "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+        "sample": f"the first {k} sub-grids of the workload stepped {reps1} times "
+                  f"({wall1:.1f} s wall, median {med1:.3f} s per step), one thread"}
+    log(f"cpu baseline {c1 / med1 / 1e6:.3f} M cell-updates/s on 1 thread")
+    if poly is not None:
+        groups, pdt, pdx = poly
+        pcells = sum(G.shape[0] * N ** 3 for N, _, G, _ in groups)
+        t_all, reps_p = 0.0, 0
+        t_start = time.time()
+        while reps_p < 2 or time.time() - t_start < args.cpu_uneven_seconds:
+            t0 = time.time()
+            for N, levels, G, _ in groups:
+                oracle.step(G, pdt, pdx, levels=levels, nthreads=threads)
+            t_all += time.time() - t0
+            reps_p += 1
+        counters = {}
+        for N, levels, G, _ in groups:
+            _, _, c = oracle.step(G, pdt, pdx, levels=levels, counters=True)
+            for key, v in c.items():
+                counters[key] = counters.get(key, 0) + int(v)
+        cpu["uneven"] = {
+            "value": round(pcells * reps_p / t_all, 1), "unit": "cell-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"the {sum(G.shape[0] for _, _, G, _ in groups)}-sub-grid polytrope "
+                      f"workload stepped {reps_p} times ({t_all:.1f} s wall)",
+            "counters": counters,
+            "counters_note": "one sequential oracle pass: cases of the limited slope and of the "
+                             "parabola constraint taken, and cells / face states with rho <= 0 or "
+                             "p <= 0 (the step has no floors)"}
+        log(f"cpu baseline (polytrope) {pcells * reps_p / t_all / 1e6:.2f} M cell-updates/s; "
+            f"counters {counters}")
+    return cpu
 
 
 def learned_leg(args, dev):
@@ -257,8 +324,14 @@ def main():
     ap.add_argument("--each-reps", type=int, default=3,
                     help="timed repetitions of the one-launch-per-sub-grid baseline")
     ap.add_argument("--cpu-reps", type=int, default=2)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="minimum wall time of the oracle measurement")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="minimum wall time of the all-cores oracle measurement")
+    ap.add_argument("--cpu-single-count", type=int, default=256,
+                    help="sub-grids of the workload the one-thread oracle measurement steps")
+    ap.add_argument("--cpu-single-seconds", type=float, default=5.0,
+                    help="minimum wall time of the one-thread oracle measurement")
+    ap.add_argument("--cpu-uneven-seconds", type=float, default=3.0,
+                    help="minimum wall time of the oracle on the polytrope workload")
     ap.add_argument("--copy-reps", type=int, default=10,
                     help="timed repetitions of a plain device copy of the input buffer")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -432,40 +505,24 @@ def main():
         "fp64": measured_fp64(version, workload_name, kname, kernel_ms),
     }
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        threads = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS", "0") or 0) \
-            or os.cpu_count() or 1
-        log(f"cpu baseline: oracle on the full batch, {threads} threads, "
-            f">= {args.cpu_seconds:.0f} s")
-        times = []
-        t_all = time.time()
-        while len(times) < max(args.cpu_reps, 1) or time.time() - t_all < args.cpu_seconds:
-            t0 = time.time()
-            oracle.step(U, dt, dx, nthreads=threads)
-            times.append(time.time() - t0)
-        med = statistics.median(times)
-        cpu = {"value": round(cells / med, 1), "unit": "cell-updates/s", "cores": threads,
-               "kind": "oracle",
-               "sample": f"the full {count}-sub-grid workload stepped {len(times)} times "
-                         f"({sum(times):.1f} s wall, median {med:.3f} s per step), "
-                         "OpenMP over sub-grids"}
-        log(f"cpu baseline {cells / med / 1e6:.2f} M cell-updates/s")
-
     learned_res = model = None
     if not args.no_learned:
         learned_res, model = learned_leg(args, dev)
 
-    uneven = serving = None
+    uneven = serving = poly = None
     if not args.no_uneven or not args.no_serving:
         del u_in, u_out
         torch.cuda.empty_cache()
-        uneven, tensors, udt, udx = uneven_leg(args, torch, hydroagg, workloads, dev, stream)
+        uneven, tensors, udt, udx, groups = uneven_leg(args, torch, hydroagg, workloads, dev, stream)
+        poly = (groups, udt, udx)
         if args.no_uneven:
             uneven = None
         if not args.no_serving:
             serving = serving_leg(args, torch, hydroagg, np, tensors, udt, udx, dev, model)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_leg(args, U, dt, dx, cells, poly)
 
     out = {
         "metric": METRIC,

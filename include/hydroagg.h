@@ -104,6 +104,10 @@ int hydro_get_tile(int32_t n, int32_t nfields, int32_t *tile);
  * 1, NULL u_in/u_out, u_out overlapping u_in (per sub-grid), dt < 0 or not
  * finite, dx <= 0 or not finite;
  * HYDRO_EHIP if a launch or copy fails.  count = 0 is a no-op success.
+ * Thread safety: any number of host threads may call hydro_step at once
+ * (each on its own stream or the same one); the library's descriptor
+ * staging slots are taken in turn and each is held until its copy and
+ * launches are enqueued, and reused only after that work has completed.
  */
 int hydro_step(const hydro_subgrid_t *sg, int32_t count, double dt, double dx,
                double *amax_dev, void *stream);
@@ -255,6 +259,21 @@ int hydro_mlp_mse(const float *y, const float *target, int32_t rows, float *dy,
 int hydro_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t n,
                    float lr, float beta1, float beta2, float eps, int32_t step,
                    void *stream);
+
+/*
+ * hydro_math_check -- diagnostic: evaluates, on the device, the reciprocal
+ * and square-root routines every hydro kernel uses (1/rho in the primitive
+ * recovery, the sound speed sqrt(gamma p / rho) and the 1/(a+ - a-) of the
+ * central-upwind flux, Section IV-B) on n caller-given arguments, so that
+ * tests can bound their error against correctly rounded IEEE results.
+ *   x          device, n doubles, each positive and normal.
+ *   recip_out  device, n doubles: recip(x[i]).
+ *   sqrt_out   device, n doubles: sqrt(x[i]).
+ * Errors: HYDRO_EINVAL for n < 0 or a NULL pointer with n > 0; HYDRO_EHIP if
+ * the launch fails.  Enqueues on `stream` (NULL = default stream).
+ */
+int hydro_math_check(const double *x, int32_t n, double *recip_out, double *sqrt_out,
+                     void *stream);
 
 /* Thread-local text of the last error on the calling thread ("" if none). */
 const char *hydro_last_error(void);

@@ -74,7 +74,14 @@ int class_of(int n, int nf) {
 constexpr int kSlots = 8;
 constexpr int kSlotCap = 1 << 16;
 
+// A slot is taken round-robin under the device mutex and then held, by its
+// own mutex, from the wait for its previous use through the fill of its
+// pinned buffer, the copy, the launches and the record of `done`: two host
+// threads that land on the same slot (more than kSlots calls in flight)
+// take turns, and the second waits for the first one's work to finish
+// before it overwrites the pinned buffer.
 struct Slot {
+  std::mutex mu;
   DevDesc* host = nullptr;  // pinned
   DevDesc* dev = nullptr;
   hipEvent_t done = nullptr;
@@ -90,6 +97,13 @@ struct DeviceState {
 
 constexpr int kMaxDevices = 16;
 DeviceState g_dev[kMaxDevices];
+
+Slot* take_slot(DeviceState* st) {
+  std::lock_guard<std::mutex> lk(st->mu);
+  Slot* slot = &st->slots[st->next];
+  st->next = (st->next + 1) % kSlots;
+  return slot;
+}
 
 int device_state(DeviceState** out) {
   int dev = 0;
@@ -267,12 +281,8 @@ int step_chunk(DeviceState* st, const hydro_subgrid_t* sg, int count, int base,
   // large classes this overlaps the partly filled last waves of their
   // grids, which one launch per class would run one after another).
   if (hydro::api::mixed_eligible(per_class)) {
-    Slot* slot;
-    {
-      std::lock_guard<std::mutex> lk(st->mu);
-      slot = &st->slots[st->next];
-      st->next = (st->next + 1) % kSlots;
-    }
+    Slot* slot = take_slot(st);
+    std::lock_guard<std::mutex> held(slot->mu);
     if (slot->used) HIP_TRY(hipEventSynchronize(slot->done));
     int off[kClasses], fill[kClasses], pos = 0;
     for (int c = 0; c < kClasses; ++c) {
@@ -305,12 +315,8 @@ int step_chunk(DeviceState* st, const hydro_subgrid_t* sg, int count, int base,
   }
   if (need_table == 0) return HYDRO_OK;
 
-  Slot* slot;
-  {
-    std::lock_guard<std::mutex> lk(st->mu);
-    slot = &st->slots[st->next];
-    st->next = (st->next + 1) % kSlots;
-  }
+  Slot* slot = take_slot(st);
+  std::lock_guard<std::mutex> held(slot->mu);
   if (slot->used) HIP_TRY(hipEventSynchronize(slot->done));
   int off[kClasses];
   int pos = 0;
@@ -741,6 +747,35 @@ int hydro_get_tile(int32_t n, int32_t nfields, int32_t* tile) {
   if (c < 0) return fail(HYDRO_EINVAL, "unsupported n=%d nfields=%d", n, nfields);
   if (!tile) return fail(HYDRO_EINVAL, "tile is NULL");
   *tile = g_tile[c].load(std::memory_order_relaxed);
+  return HYDRO_OK;
+}
+
+}  // extern "C"
+
+namespace hydro {
+// The kernels' reciprocal and square root on caller-given arguments
+// (diagnostic entry point hydro_math_check).
+__global__ void math_check_kernel(const double* __restrict__ x, int n,
+                                  double* __restrict__ r, double* __restrict__ q) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    r[i] = recip(x[i]);
+    q[i] = sqrt_pos(x[i]);
+  }
+}
+}  // namespace hydro
+
+extern "C" {
+
+int hydro_math_check(const double* x, int32_t n, double* recip_out, double* sqrt_out,
+                     void* stream) {
+  g_err[0] = '\0';
+  if (n < 0) return fail(HYDRO_EINVAL, "n %d < 0", n);
+  if (n == 0) return HYDRO_OK;
+  if (!x || !recip_out || !sqrt_out) return fail(HYDRO_EINVAL, "NULL pointer");
+  hipLaunchKernelGGL(hydro::math_check_kernel, dim3((n + 255) / 256), dim3(256), 0,
+                     (hipStream_t)stream, x, n, recip_out, sqrt_out);
+  HIP_TRY(hipGetLastError());
   return HYDRO_OK;
 }
 

@@ -19,10 +19,15 @@ constexpr double kGm1 = kGamma - 1.0;
 constexpr double kInvGm1 = 1.0 / kGm1;
 constexpr int kGhost = 3;
 
-// 1/x from the hardware estimate refined by two Newton-Raphson steps
-// (r <- r + r(1 - x r)); within an ulp or so of the rounded quotient for the
-// positive, normal arguments it is used on (densities, wave-speed spans).
-// Scaling x by a power of two scales the result exactly.
+// 1/x from the hardware estimate refined by two steps of the Newton-Raphson
+// iteration for the reciprocal, r <- r + r(1 - x r), each written with
+// fused multiply-adds (the form of P. Markstein, "Computation of elementary
+// functions on the IBM RISC System/6000 processor", IBM J. Res. Dev. 34(1),
+// 1990).  Each step squares the relative error of the estimate, so the
+// result is within one ulp of the correctly rounded quotient for positive
+// normal arguments (densities, wave-speed spans); the GPU tests bound it
+// against IEEE division over 1e-17..1e3.  Scaling x by a power of two scales
+// the result exactly.
 __device__ __forceinline__ double recip(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
@@ -31,10 +36,14 @@ __device__ __forceinline__ double recip(double x) {
   return fma(r, e, r);
 }
 
-// sqrt(y) for positive normal y: hardware 1/sqrt estimate (relative error
-// ~2^-24 on gfx950, measured), one coupled Newton iteration for
-// (sqrt(y), 1/(2 sqrt(y))) (~2^-48), and a final residual correction, which
-// squares the error again: the result is accurate to the last bits.
+// sqrt(y) for positive normal y by Goldschmidt's iteration (R. E.
+// Goldschmidt, M.Sc. thesis, MIT, 1964): from the hardware 1/sqrt estimate s
+// (relative error ~2^-24 on gfx950), g = y s approximates sqrt(y) and
+// h = s/2 approximates 1/(2 sqrt(y)); one coupled step with the residual
+// r = 1/2 - g h refines both (~2^-48), and a final Newton correction
+// g + h (y - g^2), with the residual y - g^2 taken exactly by a fused
+// multiply-add (Markstein 1990, above), squares the error again.  The GPU
+// tests bound the result against IEEE sqrt over 1e-17..1e3.
 __device__ __forceinline__ double sqrt_pos(double y) {
   const double s = __builtin_amdgcn_rsq(y);
   double g = y * s;

@@ -113,6 +113,9 @@ def lib() -> ctypes.CDLL:
         L.hydro_set_tile.restype = ctypes.c_int
         L.hydro_get_tile.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.hydro_get_tile.restype = ctypes.c_int
+        L.hydro_math_check.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p]
+        L.hydro_math_check.restype = ctypes.c_int
         L.hydro_last_error.argtypes = []
         L.hydro_last_error.restype = ctypes.c_char_p
         L.hydro_version.argtypes = []
@@ -206,6 +209,12 @@ def hydro_step_each(descs, dt: float, dx: float, amax=None, stream=None) -> None
     """Baseline: one launch per sub-grid (same kernel)."""
     arr, count = descs
     _check(lib().hydro_step_each(arr, count, float(dt), float(dx), _ptr(amax), _stream(stream)))
+
+
+def math_check(x, recip_out, sqrt_out, stream=None) -> None:
+    """The kernels' reciprocal and square root on device arrays (diagnostic)."""
+    _check(lib().hydro_math_check(_ptr(x), int(x.numel()), _ptr(recip_out), _ptr(sqrt_out),
+                                  _stream(stream)))
 
 
 def version() -> str:

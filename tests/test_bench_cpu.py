@@ -2,6 +2,8 @@
 kernels it was taken on."""
 import json
 
+import numpy as np
+
 import bench
 
 V = "hydroagg gfx950 src aaaaaaaaaaaa kernels 111111111111"
@@ -52,3 +54,20 @@ def test_fp64_rate_from_the_record(tmp_path):
     assert r["frac"] == round(10.0 / 78.6, 4)
     other = "hydroagg gfx950 src aaaaaaaaaaaa kernels 999999999999"
     assert bench.measured_fp64(other, "4096x8^3 F=11", "hydro_lds8_kernel<11,14>", 0.3, str(p)) is None
+
+
+def test_per_subgrid_metric_sees_what_the_pooled_one_cannot():
+    from tests.gpu_util import normwise, normwise_each
+    rng = np.random.default_rng(0)
+    ref = rng.uniform(0.5, 1.5, size=(3, 2, 4, 4, 4))
+    ref[1] *= 1e-10                      # a sub-grid of tiny values (atmosphere)
+    got = ref.copy()
+    got[1, 0, 2, 2, 2] *= 1 + 1e-6       # an error of 1e-6 relative inside it
+    assert normwise(got, ref).max() < 1e-12
+    each = normwise_each(got, ref)
+    assert each.shape == (3, 2)
+    assert abs(each[1, 0] - 1e-6 * ref[1, 0, 2, 2, 2] / np.abs(ref[1, 0]).max()) < 1e-12
+    assert each[0].max() == 0 and each[2].max() == 0 and each[1, 1] == 0
+    zero = np.zeros_like(ref)
+    assert normwise_each(zero, zero).max() == 0
+    assert normwise_each(zero + 1e-300, zero)[0, 0] == 1e-300

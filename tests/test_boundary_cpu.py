@@ -93,3 +93,10 @@ def test_tile_setting_is_validated_and_round_trips():
     finally:
         hydroagg.set_tile(16, 6, defaults[(16, 6)])
     assert hydroagg.get_tile(16, 6) == 8
+
+
+def test_math_check_arguments():
+    L = hydroagg.lib()
+    assert L.hydro_math_check(None, -1, None, None, None) == hydroagg.HYDRO_EINVAL
+    assert L.hydro_math_check(None, 4, None, None, None) == hydroagg.HYDRO_EINVAL
+    assert L.hydro_math_check(None, 0, None, None, None) == hydroagg.HYDRO_OK

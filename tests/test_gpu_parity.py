@@ -1,8 +1,9 @@
 """Parity of the HIP path with the CPU oracle on the same seeded inputs.
 
-Bar: per field, max |U_gpu - U_oracle| / max |U_oracle| <= 1e-12 over all
-interior cells (FP64 step; the two sides differ only in rounding order);
-amax relative error <= 1e-13.  Bitwise where the mathematics fixes the value
+Bar: per sub-grid and per field, max |U_gpu - U_oracle| / max |U_oracle| over
+that sub-grid's interior cells <= 1e-12 (FP64 step; the two sides differ only
+in rounding order), and the same pooled over the batch; amax relative error
+<= 1e-13 per sub-grid.  Bitwise where the mathematics fixes the value
 (uniform state, dt = 0, power-of-two scaling, batch independence)."""
 import math
 
@@ -10,7 +11,7 @@ import numpy as np
 import pytest
 
 from paper_2210_06438_amd import hydroagg, workloads
-from tests.gpu_util import ghost_mask, interior, normwise
+from tests.gpu_util import ghost_mask, interior, normwise, normwise_each
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -44,6 +45,8 @@ def check(U, dt, dx, oracle_mod, levels=None, each=False):
     got, amax = run_gpu(U, dt, dx, levels=levels, each=each)
     err = normwise(interior(got, n), interior(ref, n))
     assert np.all(err <= TOL), err
+    each = normwise_each(interior(got, n), interior(ref, n))
+    assert np.all(each <= TOL), (np.unravel_index(np.argmax(each), each.shape), each.max())
     rel = np.max(np.abs(amax - ref_amax) / ref_amax)
     assert rel <= ATOL_AMAX, rel
     g = ghost_mask(n)
@@ -171,7 +174,7 @@ def test_full_size_batch_sampled(dev, oracle_mod):
     sample = np.unique(np.r_[0, count - 1, np.random.default_rng(1).integers(0, count, 14)])
     got = u_out[torch.from_numpy(sample).to(dev)].cpu().numpy()
     ref, ref_amax = oracle_mod.step(U[sample], dt, 1 / 64)
-    assert np.all(normwise(interior(got, 8), interior(ref, 8)) <= TOL)
+    assert np.all(normwise_each(interior(got, 8), interior(ref, 8)) <= TOL)
     a = amax.cpu().numpy()[sample]
     assert np.max(np.abs(a - ref_amax) / ref_amax) <= ATOL_AMAX
 
@@ -251,7 +254,7 @@ def test_tiles_are_bitwise_equivalent(dev, oracle_mod, n, nf, count):
             out[tile] = check(U, 2e-3, 0.05, oracle_mod, levels=levels)
     finally:
         hydroagg.set_tile(n, nf, before)
-    diff = normwise(interior(out[4][0], n), interior(out[8][0], n))
+    diff = normwise_each(interior(out[4][0], n), interior(out[8][0], n))
     da = np.max(np.abs(out[4][1] - out[8][1]) / out[8][1])
     print(f"tile 4 vs 8: normwise {diff.max():.2e}, amax {da:.2e}", flush=True)
     assert diff.max() <= 1e-13 and da <= 1e-14
@@ -278,7 +281,7 @@ def test_plan_recaptures_after_a_tile_change(dev):
     finally:
         hydroagg.set_tile(n, nf, before)
         plan.close()
-    assert normwise(interior(got, n), interior(ref, n)).max() <= 1e-13
+    assert normwise_each(interior(got, n), interior(ref, n)).max() <= 1e-13
     assert not np.array_equal(interior(got, n), np.zeros_like(interior(got, n)))
 
 
@@ -300,7 +303,7 @@ def test_batch_larger_than_a_staging_slot(dev, oracle_mod):
     assert torch.equal(u_out, first[idx]) and torch.equal(amax, amax[:1031][idx])
     ref, ref_amax = oracle_mod.step(uniq, dt, dx)
     got = first.cpu().numpy()
-    assert np.all(normwise(interior(got, 8), interior(ref, 8)) <= TOL)
+    assert np.all(normwise_each(interior(got, 8), interior(ref, 8)) <= TOL)
     assert np.max(np.abs(amax[:1031].cpu().numpy() - ref_amax) / ref_amax) <= ATOL_AMAX
     del u_in, u_out
 
@@ -414,6 +417,40 @@ def test_mixed_batch_is_one_launch_bitwise_alone(dev, oracle_mod, tiles, nf, for
             assert np.array_equal(interior(got, n), interior(ref, n)), n
             assert np.array_equal(amax.cpu().numpy()[k:k + len(U)], ref_a), n
             o, oa = oracle_mod.step(U, dt, dx)
-            assert np.all(normwise(interior(got, n), interior(o, n)) <= TOL)
+            assert np.all(normwise_each(interior(got, n), interior(o, n)) <= TOL)
             k += len(U)
     _with_tiles(TILE_SETS[tiles], run)
+
+
+def test_concurrent_host_threads_share_the_descriptor_ring(dev):
+    """Four host threads, each on its own stream, issue 24 table-path steps
+    each (96 calls in flight against 8 staging slots): every result is
+    bitwise the single-threaded one."""
+    import threading
+    U = workloads.random_smooth(40, n=8, nfields=11, seed=1500)
+    dt, dx = 1e-3, 0.05
+    ref, ref_a = run_gpu(U, dt, dx)
+    u_in = torch.from_numpy(U).to(dev)
+    outs = [torch.zeros_like(u_in) for _ in range(4)]
+    amaxs = [torch.zeros(40, dtype=torch.float64, device=dev) for _ in range(4)]
+    descs = [hydroagg.subgrids(u_in, o) for o in outs]
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    errors = []
+
+    def work(k):
+        try:
+            for _ in range(24):
+                hydroagg.hydro_step(descs[k], dt, dx, amaxs[k], streams[k])
+        except Exception as e:          # noqa: BLE001 - reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for k in range(4):
+        assert np.array_equal(interior(outs[k].cpu().numpy(), 8), interior(ref, 8)), k
+        assert np.array_equal(amaxs[k].cpu().numpy(), ref_a), k
