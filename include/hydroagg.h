@@ -148,6 +148,82 @@ int hydro_plan_launch_graph(hydro_plan_t *plan, double dt, double dx,
 int hydro_plan_destroy(hydro_plan_t *plan);
 
 /*
+ * Bricks: a regular block of nb[0] x nb[1] x nb[2] sub-grids of one shape
+ * (edge n, nfields fields, one octree level) tiling a rectangular domain of
+ * n*nb[0] x n*nb[1] x n*nb[2] cells, each sub-grid stored as in hydro_step
+ * ([nfields][M][M][M], M = n + 6) and the sub-grids contiguous in the order
+ * s = (bz*nb[1] + by)*nb[0] + bx (x fastest).  A brick buffer holds
+ * nb[0]*nb[1]*nb[2]*nfields*M^3 doubles.  bc[d] is the boundary condition of
+ * the domain along axis d (x, y, z): HYDRO_BC_PERIODIC wraps around,
+ * HYDRO_BC_OUTFLOW continues the domain by its outermost cell (zero
+ * gradient).  This is the multi-sub-grid state of the paper's time-step,
+ * whose three solver iterations (Section VI-A) each read ghost layers that
+ * the neighbouring sub-grids' interiors fill (Section V-A: sub-grids with
+ * 3-cell ghost layers).
+ */
+#define HYDRO_BC_PERIODIC 0
+#define HYDRO_BC_OUTFLOW 1
+
+typedef struct {
+  int32_t n;       /* 8, 12 or 16                                     */
+  int32_t nfields; /* 6 or 11                                         */
+  int32_t nb[3];   /* sub-grids along x, y, z, each >= 1              */
+  int32_t bc[3];   /* HYDRO_BC_PERIODIC or HYDRO_BC_OUTFLOW per axis  */
+  int32_t level;   /* octree level of every sub-grid, 0..30           */
+} hydro_brick_t;
+
+/*
+ * hydro_ghost_fill -- set every ghost cell (faces, edges and corners) of
+ * every sub-grid of the brick buffer u, in place, to the value of the domain
+ * cell it stands for: the interior cell of the neighbouring sub-grid, or,
+ * beyond the domain, the cell given by the boundary condition of each axis
+ * applied independently.  Interior cells are only read.  Bitwise a copy.
+ * Errors: HYDRO_EINVAL for a NULL brick or buffer, an unsupported shape, a
+ * count below 1 or above 2^20 sub-grids, a bad bc or level, or a buffer not
+ * 16-byte aligned; HYDRO_EHIP if the launch fails.  Enqueues on `stream`.
+ */
+int hydro_ghost_fill(const hydro_brick_t *brick, double *u, void *stream);
+
+/*
+ * SSP-RK3 time-step on a device-resident brick: the paper's time-step of
+ * three solver iterations (Section VI-A) composed from hydro_step as the
+ * three-stage strong-stability-preserving Runge-Kutta method of Shu and
+ * Osher (J. Comput. Phys. 77, 1988), with E(V) = one hydro_step stage of V:
+ *   U1 = E(U0),  U2 = 3/4 U0 + 1/4 E(U1),  U3 = 1/3 U0 + 2/3 E(U2),
+ * each stage's result with its ghost layers refilled (hydro_ghost_fill)
+ * before the next stage reads it.
+ * hydro_rk3_create binds the brick to three caller-owned device brick
+ * buffers: u (the state, with ghosts filled on entry; it holds U3, ghosts
+ * filled, after a step) and two work buffers w and s (their contents are
+ * overwritten); it creates the plans of the two aggregated steps (E(u) into
+ * w, E(w) into s), so it allocates and belongs to set-up.  The buffers must
+ * not overlap and must stay alive until hydro_rk3_destroy.
+ * hydro_rk3_stage(rk, k, ...) runs stage k = 1, 2 or 3 alone (after stage 1
+ * and 2, w holds U1 and U2 with ghosts; after stage 3, u holds U3), so that
+ * the three calls in order are one time-step; hydro_rk3_step runs all three
+ * as launches, hydro_rk3_launch_graph as ONE hipGraph launch (captured at
+ * first use and again when dt, dx or amax_dev change; results bitwise those
+ * of hydro_rk3_step).  dt >= 0 and dx > 0 as in hydro_step; amax_dev (device,
+ * one double per sub-grid, or NULL) receives the amax of stage 1, i.e. of
+ * the state the step starts from (hydro_step's definition); the later stages
+ * write no amax.  Per step: 3 aggregated steps, 3 ghost fills, 2 stage
+ * combinations.  A time-step object may be used from one host thread at a
+ * time; hydro_rk3_destroy waits for its work.
+ * Errors: as hydro_step and hydro_ghost_fill; HYDRO_EINVAL for k outside
+ * 1..3 or overlapping buffers.
+ */
+typedef struct hydro_rk3 hydro_rk3_t;
+int hydro_rk3_create(hydro_rk3_t **out, const hydro_brick_t *brick, double *u,
+                     double *w, double *s);
+int hydro_rk3_stage(hydro_rk3_t *rk, int32_t k, double dt, double dx,
+                    double *amax_dev, void *stream);
+int hydro_rk3_step(hydro_rk3_t *rk, double dt, double dx, double *amax_dev,
+                   void *stream);
+int hydro_rk3_launch_graph(hydro_rk3_t *rk, double dt, double dx,
+                           double *amax_dev, void *stream);
+int hydro_rk3_destroy(hydro_rk3_t *rk);
+
+/*
  * Aggregator: explicit work aggregation of fine-grained sub-grid tasks (the
  * paper's strategy 3, Section V-D).  Tasks submitted while the aggregator's
  * streams are busy are held and launched together as one batch (one kernel

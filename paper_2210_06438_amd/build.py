@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libhydroagg.so")
 SOURCES = [os.path.join(HERE, "csrc", "hydro_api.hip"),
            os.path.join(HERE, "csrc", "agg_api.hip"),
-           os.path.join(HERE, "csrc", "mlp.hip")]
+           os.path.join(HERE, "csrc", "mlp.hip"),
+           os.path.join(HERE, "csrc", "rk3_api.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -577,6 +577,14 @@ void plan_free(hydro_plan* p) {
 
 }  // namespace
 
+namespace hydro {
+namespace api {
+int plan_enqueue(hydro_plan* p, double dt, double dx, double* amax, hipStream_t s) {
+  return plan_launches(p, dt, dx, amax, s);
+}
+}  // namespace api
+}  // namespace hydro
+
 extern "C" {
 
 int hydro_step(const hydro_subgrid_t* sg, int32_t count, double dt, double dx,

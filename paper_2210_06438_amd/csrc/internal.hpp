@@ -38,5 +38,9 @@ int launch_mixed(const int* num, const int* off, const DevDesc* host, const DevD
                  int n, double dt, double dx, double* amax, hipStream_t s, bool parts = false,
                  int* groups = nullptr);
 
+// The launches of one step of a plan (hydro_plan_step without its argument
+// checks) on stream s; usable inside a stream capture.
+int plan_enqueue(hydro_plan* p, double dt, double dx, double* amax, hipStream_t s);
+
 }  // namespace api
 }  // namespace hydro

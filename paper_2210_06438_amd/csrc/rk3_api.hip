@@ -1,0 +1,278 @@
+// rk3_api.hip -- host side of the device time-step on a brick of sub-grids:
+// ghost-layer fill and the three-stage SSP Runge-Kutta method of Shu and
+// Osher composed from the aggregated hydro step (the paper's time-step is
+// three solver iterations, Section VI-A; sub-grids with 3-cell ghost layers
+// filled from their neighbours, Section V-A).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/hydroagg.h"
+#include "brick.hpp"
+#include "internal.hpp"
+
+using hydro::api::fail;
+
+namespace {
+
+#define HIP_TRY(expr)                                                         \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      return fail(HYDRO_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr long kMaxBrickSubgrids = 1l << 20;
+
+long brick_count(const hydro_brick_t& b) { return (long)b.nb[0] * b.nb[1] * b.nb[2]; }
+
+long brick_doubles(const hydro_brick_t& b) {
+  const long M = b.n + 2 * HYDRO_GHOST;
+  return brick_count(b) * b.nfields * M * M * M;
+}
+
+int check_brick(const hydro_brick_t* b) {
+  if (!b) return fail(HYDRO_EINVAL, "brick is NULL");
+  if (hydro::api::class_of_task(b->n, b->nfields) < 0)
+    return fail(HYDRO_EINVAL, "unsupported n=%d nfields=%d", b->n, b->nfields);
+  for (int d = 0; d < 3; ++d) {
+    if (b->nb[d] < 1) return fail(HYDRO_EINVAL, "nb[%d] = %d < 1", d, b->nb[d]);
+    if (b->bc[d] != HYDRO_BC_PERIODIC && b->bc[d] != HYDRO_BC_OUTFLOW)
+      return fail(HYDRO_EINVAL, "bc[%d] = %d", d, b->bc[d]);
+  }
+  if (brick_count(*b) > kMaxBrickSubgrids)
+    return fail(HYDRO_EINVAL, "%ld sub-grids (at most %ld)", brick_count(*b), kMaxBrickSubgrids);
+  if (b->level < 0 || b->level > 30) return fail(HYDRO_EINVAL, "level %d", b->level);
+  return HYDRO_OK;
+}
+
+int check_buffer(const double* u, const char* what) {
+  if (!u) return fail(HYDRO_EINVAL, "%s is NULL", what);
+  if ((uintptr_t)u & 15) return fail(HYDRO_EINVAL, "%s must be 16-byte aligned", what);
+  return HYDRO_OK;
+}
+
+hydro::BrickGeo geo_of(const hydro_brick_t& b) {
+  hydro::BrickGeo g;
+  const long M = b.n + 2 * HYDRO_GHOST;
+  g.nf = b.nfields;
+  for (int d = 0; d < 3; ++d) {
+    g.nb[d] = b.nb[d];
+    g.bc[d] = b.bc[d];
+  }
+  g.sg_stride = (long)b.nfields * M * M * M;
+  return g;
+}
+
+int launch_fill(const hydro_brick_t& b, double* u, hipStream_t s) {
+  const hydro::BrickGeo g = geo_of(b);
+  const dim3 grid((unsigned)(brick_count(b) * b.nfields)), block(256);
+  switch (b.n) {
+    case 8: hipLaunchKernelGGL(hydro::ghost_fill_kernel<8>, grid, block, 0, s, u, g); break;
+    case 12: hipLaunchKernelGGL(hydro::ghost_fill_kernel<12>, grid, block, 0, s, u, g); break;
+    default: hipLaunchKernelGGL(hydro::ghost_fill_kernel<16>, grid, block, 0, s, u, g); break;
+  }
+  HIP_TRY(hipGetLastError());
+  return HYDRO_OK;
+}
+
+int launch_combine(const hydro_brick_t& b, double* out, const double* x, const double* y,
+                   double a, double c, hipStream_t s) {
+  const long M = b.n + 2 * HYDRO_GHOST;
+  const long stride = (long)b.nfields * M * M * M;
+  const dim3 grid((unsigned)(brick_count(b) * b.nfields)), block(256);
+  switch (b.n) {
+    case 8:
+      hipLaunchKernelGGL(hydro::rk_combine_kernel<8>, grid, block, 0, s, out, x, y, a, c, stride, b.nfields);
+      break;
+    case 12:
+      hipLaunchKernelGGL(hydro::rk_combine_kernel<12>, grid, block, 0, s, out, x, y, a, c, stride, b.nfields);
+      break;
+    default:
+      hipLaunchKernelGGL(hydro::rk_combine_kernel<16>, grid, block, 0, s, out, x, y, a, c, stride, b.nfields);
+      break;
+  }
+  HIP_TRY(hipGetLastError());
+  return HYDRO_OK;
+}
+
+}  // namespace
+
+struct hydro_rk3 {
+  hydro_brick_t b;
+  double* u = nullptr;
+  double* w = nullptr;
+  double* s = nullptr;
+  hydro_plan_t* step_uw = nullptr;  // E(u) -> w
+  hydro_plan_t* step_ws = nullptr;  // E(w) -> s
+  hipStream_t capture = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double g_dt = -1.0, g_dx = -1.0;
+  double* g_amax = nullptr;
+};
+
+namespace {
+
+// Stage k of the Shu-Osher form with E(V) = V + dt L(V) (one hydro step):
+//   1: w = E(u)                    (u = U0; w = U1)
+//   2: s = E(w); w = 3/4 u + 1/4 s (w = U2)
+//   3: s = E(w); u = 1/3 u + 2/3 s (u = U3)
+// each followed by the ghost fill of the buffer just formed.
+int stage(hydro_rk3* rk, int k, double dt, double dx, double* amax, hipStream_t st) {
+  int rc;
+  if (k == 1) {
+    if ((rc = hydro::api::plan_enqueue(rk->step_uw, dt, dx, amax, st))) return rc;
+    return launch_fill(rk->b, rk->w, st);
+  }
+  if ((rc = hydro::api::plan_enqueue(rk->step_ws, dt, dx, nullptr, st))) return rc;
+  if (k == 2) {
+    if ((rc = launch_combine(rk->b, rk->w, rk->u, rk->s, 0.75, 0.25, st))) return rc;
+    return launch_fill(rk->b, rk->w, st);
+  }
+  if ((rc = launch_combine(rk->b, rk->u, rk->u, rk->s, 1.0 / 3.0, 2.0 / 3.0, st))) return rc;
+  return launch_fill(rk->b, rk->u, st);
+}
+
+int check_step_args(hydro_rk3* rk, double dt, double dx) {
+  if (!rk) return fail(HYDRO_EINVAL, "time-step object is NULL");
+  if (!(dt >= 0.0) || !isfinite(dt)) return fail(HYDRO_EINVAL, "dt must be finite and >= 0");
+  if (!(dx > 0.0) || !isfinite(dx)) return fail(HYDRO_EINVAL, "dx must be finite and > 0");
+  return HYDRO_OK;
+}
+
+void rk3_free(hydro_rk3* rk) {
+  if (rk->exec) (void)hipGraphExecDestroy(rk->exec);
+  if (rk->graph) (void)hipGraphDestroy(rk->graph);
+  if (rk->capture) (void)hipStreamDestroy(rk->capture);
+  if (rk->step_uw) (void)hydro_plan_destroy(rk->step_uw);
+  if (rk->step_ws) (void)hydro_plan_destroy(rk->step_ws);
+  delete rk;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hydro_ghost_fill(const hydro_brick_t* brick, double* u, void* stream) {
+  hydro::api::clear_error();
+  int rc = check_brick(brick);
+  if (rc) return rc;
+  if ((rc = check_buffer(u, "u"))) return rc;
+  return launch_fill(*brick, u, (hipStream_t)stream);
+}
+
+int hydro_rk3_create(hydro_rk3_t** out, const hydro_brick_t* brick, double* u, double* w,
+                     double* s) {
+  hydro::api::clear_error();
+  if (!out) return fail(HYDRO_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_brick(brick);
+  if (rc) return rc;
+  if ((rc = check_buffer(u, "u")) || (rc = check_buffer(w, "w")) || (rc = check_buffer(s, "s")))
+    return rc;
+  const uintptr_t bytes = (uintptr_t)brick_doubles(*brick) * sizeof(double);
+  const uintptr_t p[3] = {(uintptr_t)u, (uintptr_t)w, (uintptr_t)s};
+  for (int i = 0; i < 3; ++i)
+    for (int j = i + 1; j < 3; ++j)
+      if (p[i] < p[j] + bytes && p[j] < p[i] + bytes)
+        return fail(HYDRO_EINVAL, "brick buffers overlap");
+  const long count = brick_count(*brick);
+  const long M = brick->n + 2 * HYDRO_GHOST;
+  const long stride = (long)brick->nfields * M * M * M;
+  std::vector<hydro_subgrid_t> a((size_t)count), c((size_t)count);
+  for (long i = 0; i < count; ++i) {
+    a[i].u_in = u + i * stride;
+    a[i].u_out = w + i * stride;
+    c[i].u_in = w + i * stride;
+    c[i].u_out = s + i * stride;
+    a[i].n = c[i].n = brick->n;
+    a[i].nfields = c[i].nfields = brick->nfields;
+    a[i].level = c[i].level = brick->level;
+    a[i].out_layout = c[i].out_layout = HYDRO_OUT_STORED;
+  }
+  hydro_rk3* rk = new hydro_rk3();
+  rk->b = *brick;
+  rk->u = u;
+  rk->w = w;
+  rk->s = s;
+  if ((rc = hydro_plan_create(&rk->step_uw, a.data(), (int32_t)count)) ||
+      (rc = hydro_plan_create(&rk->step_ws, c.data(), (int32_t)count))) {
+    rk3_free(rk);
+    return rc;
+  }
+  hipError_t e = hipStreamCreateWithFlags(&rk->capture, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    rk3_free(rk);
+    return fail(HYDRO_EHIP, "capture stream: %s", hipGetErrorString(e));
+  }
+  *out = rk;
+  return HYDRO_OK;
+}
+
+int hydro_rk3_stage(hydro_rk3_t* rk, int32_t k, double dt, double dx, double* amax_dev,
+                    void* stream) {
+  hydro::api::clear_error();
+  int rc = check_step_args(rk, dt, dx);
+  if (rc) return rc;
+  if (k < 1 || k > 3) return fail(HYDRO_EINVAL, "stage %d (1, 2 or 3)", k);
+  return stage(rk, k, dt, dx, k == 1 ? amax_dev : nullptr, (hipStream_t)stream);
+}
+
+int hydro_rk3_step(hydro_rk3_t* rk, double dt, double dx, double* amax_dev, void* stream) {
+  hydro::api::clear_error();
+  int rc = check_step_args(rk, dt, dx);
+  if (rc) return rc;
+  for (int k = 1; k <= 3; ++k)
+    if ((rc = stage(rk, k, dt, dx, k == 1 ? amax_dev : nullptr, (hipStream_t)stream))) return rc;
+  return HYDRO_OK;
+}
+
+int hydro_rk3_launch_graph(hydro_rk3_t* rk, double dt, double dx, double* amax_dev,
+                           void* stream) {
+  hydro::api::clear_error();
+  int rc = check_step_args(rk, dt, dx);
+  if (rc) return rc;
+  if (!rk->exec || rk->g_dt != dt || rk->g_dx != dx || rk->g_amax != amax_dev) {
+    if (rk->exec) {
+      (void)hipGraphExecDestroy(rk->exec);
+      rk->exec = nullptr;
+    }
+    if (rk->graph) {
+      (void)hipGraphDestroy(rk->graph);
+      rk->graph = nullptr;
+    }
+    HIP_TRY(hipStreamBeginCapture(rk->capture, hipStreamCaptureModeThreadLocal));
+    for (int k = 1; k <= 3 && rc == HYDRO_OK; ++k)
+      rc = stage(rk, k, dt, dx, k == 1 ? amax_dev : nullptr, rk->capture);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(rk->capture, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(HYDRO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    rk->graph = g;
+    HIP_TRY(hipGraphInstantiate(&rk->exec, rk->graph, nullptr, nullptr, 0));
+    rk->g_dt = dt;
+    rk->g_dx = dx;
+    rk->g_amax = amax_dev;
+  }
+  HIP_TRY(hipGraphLaunch(rk->exec, (hipStream_t)stream));
+  return HYDRO_OK;
+}
+
+int hydro_rk3_destroy(hydro_rk3_t* rk) {
+  hydro::api::clear_error();
+  if (!rk) return HYDRO_OK;
+  int rc = HYDRO_OK;
+  if (hipDeviceSynchronize() != hipSuccess) rc = fail(HYDRO_EHIP, "hipDeviceSynchronize failed");
+  rk3_free(rk);
+  return rc;
+}
+
+}  // extern "C"

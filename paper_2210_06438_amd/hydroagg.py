@@ -64,6 +64,14 @@ class hydro_serve_stats_t(ctypes.Structure):
                 ("first_admit_us", ctypes.c_double), ("max_live", ctypes.c_uint64),
                 ("slab_waits", ctypes.c_uint64), ("launch_host_us", ctypes.c_double)]
 
+class hydro_brick_t(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nfields", ctypes.c_int32), ("nb", ctypes.c_int32 * 3),
+                ("bc", ctypes.c_int32 * 3), ("level", ctypes.c_int32)]
+
+
+BC_PERIODIC = 0
+BC_OUTFLOW = 1
+
 _lib = None
 
 
@@ -113,6 +121,19 @@ def lib() -> ctypes.CDLL:
         L.hydro_set_tile.restype = ctypes.c_int
         L.hydro_get_tile.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.hydro_get_tile.restype = ctypes.c_int
+        BP = ctypes.POINTER(hydro_brick_t)
+        L.hydro_ghost_fill.argtypes = [BP, ctypes.c_void_p, ctypes.c_void_p]
+        L.hydro_rk3_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), BP, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p]
+        L.hydro_rk3_stage.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+        for name in ("hydro_rk3_step", "hydro_rk3_launch_graph"):
+            getattr(L, name).argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_void_p, ctypes.c_void_p]
+        L.hydro_rk3_destroy.argtypes = [ctypes.c_void_p]
+        for name in ("hydro_ghost_fill", "hydro_rk3_create", "hydro_rk3_stage", "hydro_rk3_step",
+                     "hydro_rk3_launch_graph", "hydro_rk3_destroy"):
+            getattr(L, name).restype = ctypes.c_int
         L.hydro_math_check.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p]
         L.hydro_math_check.restype = ctypes.c_int
@@ -215,6 +236,55 @@ def math_check(x, recip_out, sqrt_out, stream=None) -> None:
     """The kernels' reciprocal and square root on device arrays (diagnostic)."""
     _check(lib().hydro_math_check(_ptr(x), int(x.numel()), _ptr(recip_out), _ptr(sqrt_out),
                                   _stream(stream)))
+
+
+def brick(n, nfields, nb, bc, level=0) -> hydro_brick_t:
+    """A brick descriptor: nb = (sub-grids along x, y, z), bc = per-axis
+    BC_PERIODIC / BC_OUTFLOW."""
+    b = hydro_brick_t()
+    b.n, b.nfields, b.level = int(n), int(nfields), int(level)
+    for d in range(3):
+        b.nb[d] = int(nb[d])
+        b.bc[d] = int(bc[d])
+    return b
+
+
+def ghost_fill(b: hydro_brick_t, u, stream=None) -> None:
+    """Fill every ghost cell of the brick buffer u (in place)."""
+    _check(lib().hydro_ghost_fill(ctypes.byref(b), _ptr(u), _stream(stream)))
+
+
+class RK3:
+    """SSP-RK3 time-step on a device-resident brick (hydro_rk3_*): u holds
+    the state, w and s are work buffers, all brick-sized device tensors."""
+
+    def __init__(self, b: hydro_brick_t, u, w, s):
+        self._keep = (b, u, w, s)
+        h = ctypes.c_void_p()
+        _check(lib().hydro_rk3_create(ctypes.byref(h), ctypes.byref(b), _ptr(u), _ptr(w), _ptr(s)))
+        self._h = h
+
+    def stage(self, k: int, dt: float, dx: float, amax=None, stream=None) -> None:
+        _check(lib().hydro_rk3_stage(self._h, int(k), float(dt), float(dx), _ptr(amax),
+                                     _stream(stream)))
+
+    def step(self, dt: float, dx: float, amax=None, stream=None) -> None:
+        _check(lib().hydro_rk3_step(self._h, float(dt), float(dx), _ptr(amax), _stream(stream)))
+
+    def graph(self, dt: float, dx: float, amax=None, stream=None) -> None:
+        _check(lib().hydro_rk3_launch_graph(self._h, float(dt), float(dx), _ptr(amax),
+                                            _stream(stream)))
+
+    def close(self) -> None:
+        if self._h:
+            h, self._h = self._h, None
+            _check(lib().hydro_rk3_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version() -> str:

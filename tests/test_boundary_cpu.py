@@ -100,3 +100,34 @@ def test_math_check_arguments():
     assert L.hydro_math_check(None, -1, None, None, None) == hydroagg.HYDRO_EINVAL
     assert L.hydro_math_check(None, 4, None, None, None) == hydroagg.HYDRO_EINVAL
     assert L.hydro_math_check(None, 0, None, None, None) == hydroagg.HYDRO_OK
+
+
+def test_brick_arguments_are_rejected_before_any_gpu_call():
+    L = hydroagg.lib()
+    good = dict(n=8, nf=6, nb=(2, 2, 2), bc=(0, 0, 0), level=0)
+    bad = [dict(n=10), dict(nf=7), dict(nb=(0, 1, 1)), dict(nb=(1, -1, 1)), dict(bc=(0, 2, 0)),
+           dict(bc=(-1, 0, 0)), dict(level=31), dict(nb=(1024, 1024, 2))]
+    for kw in bad:
+        a = {**good, **kw}
+        b = hydroagg.brick(a["n"], a["nf"], a["nb"], a["bc"], a["level"])
+        assert L.hydro_ghost_fill(ctypes.byref(b), 0x100000, None) == hydroagg.HYDRO_EINVAL, kw
+        h = ctypes.c_void_p()
+        assert L.hydro_rk3_create(ctypes.byref(h), ctypes.byref(b), 0x100000, 0x20000000,
+                                  0x40000000) == hydroagg.HYDRO_EINVAL, kw
+    b = hydroagg.brick(8, 6, (2, 2, 2), (0, 0, 0))
+    assert L.hydro_ghost_fill(None, 0x100000, None) == hydroagg.HYDRO_EINVAL
+    assert L.hydro_ghost_fill(ctypes.byref(b), 0, None) == hydroagg.HYDRO_EINVAL
+    assert L.hydro_ghost_fill(ctypes.byref(b), 0x100008, None) == hydroagg.HYDRO_EINVAL
+    h = ctypes.c_void_p()
+    size = 8 * 6 * 14 ** 3 * 8
+    # overlapping buffers, a NULL buffer, a NULL out pointer
+    assert L.hydro_rk3_create(ctypes.byref(h), ctypes.byref(b), 0x100000, 0x100000 + size - 8,
+                              0x40000000) == hydroagg.HYDRO_EINVAL
+    assert L.hydro_rk3_create(ctypes.byref(h), ctypes.byref(b), 0x100000, 0,
+                              0x40000000) == hydroagg.HYDRO_EINVAL
+    assert L.hydro_rk3_create(None, ctypes.byref(b), 0x100000, 0x20000000,
+                              0x40000000) == hydroagg.HYDRO_EINVAL
+    for fn in (L.hydro_rk3_step, L.hydro_rk3_launch_graph):
+        assert fn(None, 0.1, 0.1, None, None) == hydroagg.HYDRO_EINVAL
+    assert L.hydro_rk3_stage(None, 1, 0.1, 0.1, None, None) == hydroagg.HYDRO_EINVAL
+    assert L.hydro_rk3_destroy(None) == hydroagg.HYDRO_OK
