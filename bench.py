@@ -147,6 +147,51 @@ def uneven_leg(args, torch, hydroagg, workloads, dev, stream):
     return res, tensors, dt, dx, groups
 
 
+def timestep_leg(args, torch, hydroagg, workloads, dev, stream):
+    """The paper's time-step shape (Table II: 512 sub-grids of 8^3 tiling a
+    64^3 domain; three solver iterations per step, Section VI-A): one SSP-RK3
+    time-step -- 3 aggregated steps, 3 ghost fills, 2 stage combinations --
+    as ONE hipGraph launch on the device-resident brick."""
+    per_axis, n, nf = 8, 8, args.nfields
+    log(f"time-step: {per_axis ** 3} sub-grids of {n}^3, F={nf}, periodic brick")
+    U = workloads.brick(seed=7, n=n, per_axis=per_axis, nfields=nf)
+    count = U.shape[0]
+    dx = 1.0 / (per_axis * n)
+    u = torch.from_numpy(U).to(dev)
+    w, s_ = torch.empty_like(u), torch.empty_like(u)
+    amax = torch.zeros(count, dtype=torch.float64, device=dev)
+    probe = torch.empty_like(u)
+    hydroagg.hydro_step(hydroagg.subgrids(u, probe), 0.0, dx, amax, stream)
+    torch.cuda.synchronize()
+    dt = 0.4 * dx / float(amax.max())
+    del probe
+    rk = hydroagg.RK3(hydroagg.brick(n, nf, (per_axis,) * 3, (0, 0, 0)), u, w, s_)
+    for _ in range(max(args.warmup, 5)):
+        rk.graph(dt, dx, amax, stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.timestep_steps):
+        rk.graph(dt, dx, amax, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.timestep_steps
+    rk.close()
+    cells = count * n ** 3
+    log(f"time-step: {ms * 1e3:.1f} us per SSP-RK3 step ({cells / (ms * 1e-3) / 1e6:.1f} M cell-steps/s)")
+    return {"workload": f"{count} sub-grids of {n}^3 (+3 ghost layers) tiling a periodic "
+                        f"{per_axis * n}^3 domain, {nf} FP64 fields, random smooth state",
+            "what": "one SSP-RK3 time-step = 3 aggregated hydro steps + 3 ghost fills + 2 stage "
+                    "combinations, one hipGraph launch",
+            "ms_per_timestep": round(ms, 5), "timesteps": args.timestep_steps,
+            "cell_steps_per_s": round(cells / (ms * 1e-3), 1),
+            "cell_updates_per_s": round(3 * cells / (ms * 1e-3), 1),
+            "paper_context": "whole-application time per step of the 64^3 Sedov run: 86.6 ms "
+                             "(A100, best aggregation), 130 ms (MI100); kernels, ghost exchange "
+                             "and CPU work included there, device kernels only here"}
+
+
 def _time_oracle(oracle, U, dt, dx, threads, seconds, levels=None, reps=2):
     """Median wall time of oracle.step over repetitions lasting >= seconds."""
     times = []
@@ -357,6 +402,8 @@ def main():
     ap.add_argument("--interior-leg", type=int, default=1,
                     help="1: also time the headline step with interior-only outputs")
     ap.add_argument("--learned-splits", type=int, default=10)
+    ap.add_argument("--no-timestep", action="store_true", help="skip the SSP-RK3 time-step leg")
+    ap.add_argument("--timestep-steps", type=int, default=50)
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads (0 = OMP_NUM_THREADS or all cores)")
     args = ap.parse_args()
@@ -520,6 +567,10 @@ def main():
         if not args.no_serving:
             serving = serving_leg(args, torch, hydroagg, np, tensors, udt, udx, dev, model)
 
+    timestep = None
+    if not args.no_timestep:
+        timestep = timestep_leg(args, torch, hydroagg, workloads, dev, stream)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_leg(args, U, dt, dx, cells, poly)
@@ -555,6 +606,7 @@ def main():
         "uneven": uneven,
         "serving": serving,
         "learned_width": learned_res,
+        "timestep": timestep,
         "tile_autotune": tiles,
     }
     plan.close()

@@ -8,10 +8,8 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libhydroagg.so")
-SOURCES = [os.path.join(HERE, "csrc", "hydro_api.hip"),
-           os.path.join(HERE, "csrc", "agg_api.hip"),
-           os.path.join(HERE, "csrc", "mlp.hip"),
-           os.path.join(HERE, "csrc", "rk3_api.hip")]
+# every translation unit of the library: csrc/*.hip
+SOURCES = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -348,6 +348,13 @@ namespace hydro {
 namespace api {
 int class_of_task(int n, int nf) { return class_of(n, nf); }
 
+int launch_class_table(int cls, const DevDesc* table, int n, double dt, double dx, double* amax,
+                       hipStream_t s) {
+  return dispatch_table(cls, table, n, dt, dx, amax, s);
+}
+
+DevDesc device_desc(const hydro_subgrid_t& sg, int index) { return to_dev(sg, index); }
+
 bool mixed_eligible(const int* num) {
   int present = 0, f = -1;
   for (int c = 0; c < kClasses; ++c) {

@@ -18,6 +18,14 @@ void clear_error();
 int class_of_task(int n, int nf);
 constexpr int kNumClasses = 6;
 
+// One table launch of shape class `cls` (current tile) over n sub-grids
+// whose descriptors are table[0..n).
+int launch_class_table(int cls, const DevDesc* table, int n, double dt, double dx, double* amax,
+                       hipStream_t s);
+
+// Device descriptor of task `sg` at batch position `index`.
+DevDesc device_desc(const hydro_subgrid_t& sg, int index);
+
 // Argument checks of hydro_step (0 or HYDRO_EINVAL).
 int validate_batch(const hydro_subgrid_t* sg, int32_t count, double dt, double dx);
 
