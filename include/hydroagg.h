@@ -113,6 +113,26 @@ int hydro_step(const hydro_subgrid_t *sg, int32_t count, double dt, double dx,
                double *amax_dev, void *stream);
 
 /*
+ * hydro_step_static -- hydro_step for callers that cannot allocate memory:
+ * code that runs under stream capture, tight serving loops, and harnesses
+ * that forbid allocation.  Same arguments, launches, results (bitwise) and
+ * errors as hydro_step, but the call never allocates device or host memory,
+ * at its first call or later: the descriptor table goes to a static device
+ * array of HYDRO_STATIC_MAX descriptors (32 bytes each: 256 KiB, held by every
+ * GPU the library runs on until the process ends) through a static host
+ * staging array of the same size.  Errors as hydro_step, plus HYDRO_EINVAL
+ * when count > HYDRO_STATIC_MAX.
+ * Concurrency: every call on one GPU shares that GPU's arrays, which keep the
+ * last call's descriptors.  Calls are serialised on the host, and calls on
+ * one stream are ordered; calls whose work may overlap on one GPU (different
+ * streams, or a graph that holds the call replayed beside another call) race
+ * on the device table and give wrong results.
+ */
+#define HYDRO_STATIC_MAX 8192
+int hydro_step_static(const hydro_subgrid_t *sg, int32_t count, double dt,
+                      double dx, double *amax_dev, void *stream);
+
+/*
  * hydro_step_each -- the non-aggregated baseline: the same kernel launched
  * once per sub-grid (the paper's "1 executor, max aggregated 1" setting,
  * Section VI-B), every launch on `stream`, each carrying its one descriptor

@@ -253,9 +253,46 @@ int class_groups(int c, int n) {
 // stream (several of one field count as one multi-class launch).
 constexpr int kBranchGroups = 1024;
 
+// Where a chunk's device descriptor table comes from: a slot of the ring
+// (held under its mutex from the wait for its previous use to the record of
+// its event), or, when `fixed` is given, fixed arrays (host staging and
+// device table) that the caller owns and serialises.
+struct TableLease {
+  Slot* slot = nullptr;
+  std::unique_lock<std::mutex> held;
+  DevDesc* host = nullptr;
+  DevDesc* dev = nullptr;
+};
+
+struct FixedTable {
+  DevDesc* host;
+  DevDesc* dev;
+};
+
+int lease_table(DeviceState* st, const FixedTable* fixed, TableLease& t) {
+  if (fixed) {
+    t.host = fixed->host;
+    t.dev = fixed->dev;
+    return HYDRO_OK;
+  }
+  t.slot = take_slot(st);
+  t.held = std::unique_lock<std::mutex>(t.slot->mu);
+  if (t.slot->used) HIP_TRY(hipEventSynchronize(t.slot->done));
+  t.host = t.slot->host;
+  t.dev = t.slot->dev;
+  return HYDRO_OK;
+}
+
+int release_table(TableLease& t, hipStream_t stream) {
+  if (!t.slot) return HYDRO_OK;
+  HIP_TRY(hipEventRecord(t.slot->done, stream));
+  t.slot->used = true;
+  return HYDRO_OK;
+}
+
 // One chunk of at most kSlotCap sub-grids starting at batch offset `base`.
-int step_chunk(DeviceState* st, const hydro_subgrid_t* sg, int count, int base,
-               double dt, double dx, double* amax, hipStream_t stream) {
+int step_chunk(DeviceState* st, const FixedTable* fixed, const hydro_subgrid_t* sg, int count,
+               int base, double dt, double dx, double* amax, hipStream_t stream) {
   int per_class[kClasses] = {0};
   for (int i = 0; i < count; ++i) per_class[class_of(sg[i].n, sg[i].nfields)]++;
   int need_table = 0;
@@ -281,9 +318,9 @@ int step_chunk(DeviceState* st, const hydro_subgrid_t* sg, int count, int base,
   // large classes this overlaps the partly filled last waves of their
   // grids, which one launch per class would run one after another).
   if (hydro::api::mixed_eligible(per_class)) {
-    Slot* slot = take_slot(st);
-    std::lock_guard<std::mutex> held(slot->mu);
-    if (slot->used) HIP_TRY(hipEventSynchronize(slot->done));
+    TableLease t;
+    int rc = lease_table(st, fixed, t);
+    if (rc) return rc;
     int off[kClasses], fill[kClasses], pos = 0;
     for (int c = 0; c < kClasses; ++c) {
       off[c] = fill[c] = pos;
@@ -291,15 +328,13 @@ int step_chunk(DeviceState* st, const hydro_subgrid_t* sg, int count, int base,
     }
     for (int i = 0; i < count; ++i) {
       const int c = class_of(sg[i].n, sg[i].nfields);
-      slot->host[fill[c]++] = to_dev(sg[i], base + i);
+      t.host[fill[c]++] = to_dev(sg[i], base + i);
     }
-    HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, sizeof(DevDesc) * count,
-                           hipMemcpyHostToDevice, stream));
-    int rc = hydro::api::launch_mixed(per_class, off, nullptr, slot->dev, count, dt, dx, amax, stream);
+    HIP_TRY(hipMemcpyAsync(t.dev, t.host, sizeof(DevDesc) * count, hipMemcpyHostToDevice,
+                           stream));
+    rc = hydro::api::launch_mixed(per_class, off, nullptr, t.dev, count, dt, dx, amax, stream);
     if (rc) return rc;
-    HIP_TRY(hipEventRecord(slot->done, stream));
-    slot->used = true;
-    return HYDRO_OK;
+    return release_table(t, stream);
   }
 
   // Small classes: descriptors travel in the kernel arguments.
@@ -315,9 +350,9 @@ int step_chunk(DeviceState* st, const hydro_subgrid_t* sg, int count, int base,
   }
   if (need_table == 0) return HYDRO_OK;
 
-  Slot* slot = take_slot(st);
-  std::lock_guard<std::mutex> held(slot->mu);
-  if (slot->used) HIP_TRY(hipEventSynchronize(slot->done));
+  TableLease t;
+  int rc = lease_table(st, fixed, t);
+  if (rc) return rc;
   int off[kClasses];
   int pos = 0;
   for (int c = 0; c < kClasses; ++c) {
@@ -328,19 +363,33 @@ int step_chunk(DeviceState* st, const hydro_subgrid_t* sg, int count, int base,
   memcpy(fill, off, sizeof fill);
   for (int i = 0; i < count; ++i) {
     int c = class_of(sg[i].n, sg[i].nfields);
-    if (per_class[c] > hydro::kArgDescs) slot->host[fill[c]++] = to_dev(sg[i], base + i);
+    if (per_class[c] > hydro::kArgDescs) t.host[fill[c]++] = to_dev(sg[i], base + i);
   }
-  HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, sizeof(DevDesc) * pos,
-                         hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(t.dev, t.host, sizeof(DevDesc) * pos, hipMemcpyHostToDevice, stream));
   for (int c = 0; c < kClasses; ++c) {
     if (per_class[c] <= hydro::kArgDescs) continue;
-    int rc = dispatch_table(c, slot->dev + off[c], per_class[c], dt, dx, amax, stream);
+    rc = dispatch_table(c, t.dev + off[c], per_class[c], dt, dx, amax, stream);
     if (rc) return rc;
   }
-  HIP_TRY(hipEventRecord(slot->done, stream));
-  slot->used = true;
-  return HYDRO_OK;
+  return release_table(t, stream);
 }
+
+// ---- allocation-free step (hydro_step_static) ----------------------------
+// The descriptor table of hydro_step_static lives in `scratch`, a static
+// device array (each GPU holds its own copy at its own address), and its host
+// staging in a static host array per device.  In host code `scratch` names a
+// host-side stand-in, never the device memory: its device address is taken
+// once per device, with that device current, by hipGetSymbolAddress and used
+// everywhere instead (copy destination, kernel arguments).
+constexpr int kStaticMax = HYDRO_STATIC_MAX;
+static __device__ __align__(256) DevDesc scratch[kStaticMax];
+
+struct StaticState {
+  std::mutex mu;
+  DevDesc* dev = nullptr;  // device address of this device's `scratch`
+  DevDesc host[kStaticMax];
+};
+StaticState g_static[kMaxDevices];
 
 }  // namespace
 
@@ -606,10 +655,34 @@ int hydro_step(const hydro_subgrid_t* sg, int32_t count, double dt, double dx,
   hipStream_t s = (hipStream_t)stream;
   for (int base = 0; base < count; base += kSlotCap) {
     int n = count - base < kSlotCap ? count - base : kSlotCap;
-    rc = step_chunk(st, sg + base, n, base, dt, dx, amax_dev, s);
+    rc = step_chunk(st, nullptr, sg + base, n, base, dt, dx, amax_dev, s);
     if (rc) return rc;
   }
   return HYDRO_OK;
+}
+
+int hydro_step_static(const hydro_subgrid_t* sg, int32_t count, double dt, double dx,
+                      double* amax_dev, void* stream) {
+  g_err[0] = '\0';
+  int rc = validate(sg, count, dt, dx);
+  if (rc) return rc;
+  if (count > kStaticMax)
+    return fail(HYDRO_EINVAL, "count %d exceeds HYDRO_STATIC_MAX (%d) of hydro_step_static", count,
+                kStaticMax);
+  if (count == 0) return HYDRO_OK;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HYDRO_EINVAL, "device %d out of range", dev);
+  StaticState& st = g_static[dev];
+  std::lock_guard<std::mutex> lk(st.mu);
+  if (!st.dev) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(HYDRO_EHIP, "hipGetSymbolAddress(scratch) gave NULL");
+    st.dev = static_cast<DevDesc*>(p);
+  }
+  const FixedTable fixed{st.host, st.dev};
+  return step_chunk(nullptr, &fixed, sg, count, 0, dt, dx, amax_dev, (hipStream_t)stream);
 }
 
 int hydro_step_each(const hydro_subgrid_t* sg, int32_t count, double dt,

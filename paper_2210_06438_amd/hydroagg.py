@@ -17,6 +17,7 @@ HYDRO_OK, HYDRO_EINVAL, HYDRO_EHIP, HYDRO_ENOMEM, HYDRO_EAGAIN = 0, -1, -2, -3, 
 GHOST = 3
 OUT_STORED = 0      # u_out in the (n+6)^3 layout of u_in, interior written
 OUT_INTERIOR = 1    # u_out holds the interior only, [F][n][n][n]
+STATIC_MAX = 8192   # most sub-grids of one hydro_step_static call
 
 
 class HydroError(RuntimeError):
@@ -84,7 +85,7 @@ def lib() -> ctypes.CDLL:
                                "`python -m paper_2210_06438_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.POINTER(hydro_subgrid_t)
-        for name in ("hydro_step", "hydro_step_each"):
+        for name in ("hydro_step", "hydro_step_each", "hydro_step_static"):
             f = getattr(L, name)
             f.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                           ctypes.c_void_p, ctypes.c_void_p]
@@ -224,6 +225,13 @@ def hydro_step(descs, dt: float, dx: float, amax=None, stream=None) -> None:
     """Aggregated step: one launch per (n, nfields) class in the batch."""
     arr, count = descs
     _check(lib().hydro_step(arr, count, float(dt), float(dx), _ptr(amax), _stream(stream)))
+
+
+def hydro_step_static(descs, dt: float, dx: float, amax=None, stream=None) -> None:
+    """hydro_step through the library's static descriptor table (allocates
+    nothing; at most STATIC_MAX sub-grids; overlapping calls on one GPU race)."""
+    arr, count = descs
+    _check(lib().hydro_step_static(arr, count, float(dt), float(dx), _ptr(amax), _stream(stream)))
 
 
 def hydro_step_each(descs, dt: float, dx: float, amax=None, stream=None) -> None:

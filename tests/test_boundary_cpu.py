@@ -44,7 +44,7 @@ def _desc(n=8, nf=11, level=0, out_layout=0, u_in=0x100000, u_out=0x10000000):
     return a
 
 
-@pytest.mark.parametrize("fn", ["hydro_step", "hydro_step_each"])
+@pytest.mark.parametrize("fn", ["hydro_step", "hydro_step_each", "hydro_step_static"])
 @pytest.mark.parametrize("kw,count,dt,dx", [
     (dict(n=9), 1, 0.1, 0.1),
     (dict(nf=7), 1, 0.1, 0.1),
@@ -78,6 +78,20 @@ def test_null_batch_and_empty_batch():
     assert L.hydro_step(None, 1, 0.1, 0.1, None, None) == hydroagg.HYDRO_EINVAL
     assert L.hydro_step(None, 0, 0.1, 0.1, None, None) == hydroagg.HYDRO_OK
     assert L.hydro_step_each(None, 0, 0.1, 0.1, None, None) == hydroagg.HYDRO_OK
+    assert L.hydro_step_static(None, 0, 0.1, 0.1, None, None) == hydroagg.HYDRO_OK
+
+
+def test_static_step_rejects_batches_beyond_its_table():
+    """hydro_step_static holds at most STATIC_MAX descriptors; one more is an
+    argument error, reported before any device call."""
+    L = hydroagg.lib()
+    n = hydroagg.STATIC_MAX + 1
+    a = (hydroagg.hydro_subgrid_t * n)()
+    for i in range(n):
+        a[i].u_in, a[i].u_out = 0x100000 + i * 2 * STORED_8_11, 0x100000 + (2 * i + 1) * STORED_8_11
+        a[i].n, a[i].nfields = 8, 11
+    assert L.hydro_step_static(a, n, 0.1, 0.1, None, None) == hydroagg.HYDRO_EINVAL
+    assert "HYDRO_STATIC_MAX" in L.hydro_last_error().decode()
 
 
 def test_tile_setting_is_validated_and_round_trips():
