@@ -4,7 +4,9 @@ Default workload: 4096 independent sub-grids of 8^3 cells (+3 ghost layers,
 14^3 stored), 11 FP64 fields, the random smooth state (seeded), dx = 1/64,
 dt from a dt = 0 pass at Courant number 0.4.  One timed step = one stage of
 the step over the whole batch, issued as ONE hipGraph launch of the
-aggregated kernel (inputs resident in HBM before the timed region).
+aggregated kernel (inputs resident in HBM before the timed region), each
+sub-grid's updated interior written to [F][n][n][n] (the stored (n+6)^3
+output layout is timed beside it).
 
 Also measured, on the same GPU and inputs: the same kernel launched once per
 sub-grid (4096 launches, the non-aggregated baseline), and the CPU oracle on
@@ -95,12 +97,15 @@ def uneven_leg(args, torch, hydroagg, workloads, dev, stream):
     dx = 0.5
     log("uneven: generating 3000 polytrope sub-grids")
     groups = workloads.polytrope(count=args.uneven_count, seed=3)
-    tensors, descs, cells, tile_bytes = [], [], 0, 0
+    tensors, descs, interiors, cells, tile_bytes = [], [], [], 0, 0
     for N, levels, U, _ in groups:
         t_in = torch.from_numpy(U).to(dev)
         t_out = t_in.clone()
         tensors.append((N, levels, t_in, t_out))
-        descs.append(hydroagg.subgrids(t_in, t_out, levels=levels))
+        # the step's output: updated interiors [F][n][n][n], as in the headline
+        t_int = torch.empty((U.shape[0], U.shape[1], N, N, N), dtype=torch.float64, device=dev)
+        interiors.append(t_int)
+        descs.append(hydroagg.subgrids(t_in, t_int, levels=levels))
         cells += U.shape[0] * N ** 3
         tile_bytes += U.shape[0] * bytes_per_subgrid(N, U.shape[1])[1]
     batch = hydroagg.concat(*descs)
@@ -130,12 +135,14 @@ def uneven_leg(args, torch, hydroagg, workloads, dev, stream):
         torch.cuda.synchronize()
         each_ms = e0.elapsed_time(e1)
     plan.close()
+    del interiors
     mix = {int(N): int(t.shape[0]) for N, _, t, _ in tensors}
     log(f"uneven: {ms * 1e3:.1f} us/step, {cells / ms / 1e6:.3f} G cell-updates/s; "
         f"per-sub-grid launches {each_ms} ms")
     res = {
         "workload": f"{count} polytrope sub-grids, edges {mix}, 11 FP64 fields, random octree "
-                    "levels 2-5, one hipGraph launch per step",
+                    "levels 2-5, one hipGraph launch per step, updated interiors written "
+                    "[F][n][n][n]",
         "value": round(cells / (ms * 1e-3), 1), "unit": "cell-updates/s",
         "ms_per_step": round(ms, 5), "cells": cells,
         "achieved_gbs": round(tile_bytes / (ms * 1e-3) / 1e9, 1),
@@ -399,8 +406,10 @@ def main():
                     help="1: choose every class's tile with the autotuner first (else the defaults)")
     ap.add_argument("--tile-count", type=int, default=512,
                     help="sub-grids per class in the tile sweep")
-    ap.add_argument("--interior-leg", type=int, default=1,
-                    help="1: also time the headline step with interior-only outputs")
+    ap.add_argument("--stored-leg", type=int, default=1,
+                    help="1: also time the headline step writing the stored (n+6)^3 layout")
+    ap.add_argument("--pattern-leg", type=int, default=1,
+                    help="1: also time the step's access pattern without its arithmetic")
     ap.add_argument("--learned-splits", type=int, default=10)
     ap.add_argument("--no-timestep", action="store_true", help="skip the SSP-RK3 time-step leg")
     ap.add_argument("--timestep-steps", type=int, default=50)
@@ -430,7 +439,9 @@ def main():
     U = workloads.random_smooth(count, n=n, nfields=nf, seed=2)
     log(f"generated in {time.time() - t0:.1f}s ({U.nbytes / 1e9:.2f} GB)")
     u_in = torch.from_numpy(U).to(dev)
-    u_out = u_in.clone()
+    # the step's output: each sub-grid's updated interior, [F][n][n][n] (the
+    # interior-only layout; the stored (n+6)^3 layout is timed beside it)
+    u_out = torch.empty((count, nf, n, n, n), dtype=torch.float64, device=dev)
     amax = torch.zeros(count, dtype=torch.float64, device=dev)
     descs = hydroagg.subgrids(u_in, u_out)
     plan = hydroagg.Plan(descs)
@@ -480,23 +491,51 @@ def main():
     kernel_ms = statistics.mean(a_.elapsed_time(b_) for a_, b_ in ev)
     log(f"kernel duration (per-launch events): {kernel_ms * 1e3:.1f} us")
 
-    # ---- the same step writing interior-only outputs (reported beside) -----
-    interior_ms = None
-    if args.interior_leg:
-        u_int = torch.empty((count, nf, n, n, n), dtype=torch.float64, device=dev)
-        plan_i = hydroagg.Plan(hydroagg.subgrids(u_in, u_int))
+    # ---- the step's data movement alone: the access pattern without the
+    # arithmetic, at the step's occupancy and at the occupancy registers allow
+    pattern = None
+    if args.pattern_leg:
+        pattern = {}
+        for same, key in ((True, "same_occupancy_us"), (False, "register_limited_us")):
+            for _ in range(3):
+                plan.pattern_floor(same, stream)
+            pev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(args.steps)]
+            for a_, b_ in pev:
+                a_.record(stream)
+                plan.pattern_floor(same, stream)
+                b_.record(stream)
+            torch.cuda.synchronize()
+            pattern[key] = round(1e3 * statistics.mean(a_.elapsed_time(b_) for a_, b_ in pev), 2)
+        pattern["step_over_pattern"] = round(kernel_ms * 1e3 / pattern["same_occupancy_us"], 3)
+        log(f"access pattern alone: {pattern['same_occupancy_us']} us at the step's occupancy, "
+            f"{pattern['register_limited_us']} us with no LDS limit")
+
+    # ---- the same step writing the stored (n+6)^3 layout (reported beside) --
+    stored_ms = stored_kernel_ms = None
+    if args.stored_leg:
+        u_st = u_in.clone()
+        plan_s = hydroagg.Plan(hydroagg.subgrids(u_in, u_st))
         for _ in range(args.warmup):
-            plan_i.graph(dt, dx, amax, stream)
+            plan_s.graph(dt, dx, amax, stream)
         torch.cuda.synchronize()
         e0.record(stream)
         for _ in range(args.steps):
-            plan_i.graph(dt, dx, amax, stream)
+            plan_s.graph(dt, dx, amax, stream)
         e1.record(stream)
         torch.cuda.synchronize()
-        interior_ms = e0.elapsed_time(e1) / args.steps
-        plan_i.close()
-        del u_int
-        log(f"interior-only outputs: {interior_ms * 1e3:.1f} us/step")
+        stored_ms = e0.elapsed_time(e1) / args.steps
+        sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for a_, b_ in sev:
+            a_.record(stream)
+            plan_s.graph(dt, dx, amax, stream)
+            b_.record(stream)
+        torch.cuda.synchronize()
+        stored_kernel_ms = statistics.mean(a_.elapsed_time(b_) for a_, b_ in sev)
+        plan_s.close()
+        del u_st
+        log(f"stored-layout outputs: {stored_ms * 1e3:.1f} us/step, kernel {stored_kernel_ms * 1e3:.1f} us")
 
     # ---- baseline: the same kernel, one launch per sub-grid ----------------
     each_ms = None
@@ -514,13 +553,15 @@ def main():
     # ---- a plain device copy of the same buffer: measured bandwidth reference
     copy_gbs = None
     if args.copy_reps > 0:
-        u_out.copy_(u_in)
+        u_cp = torch.empty_like(u_in)
+        u_cp.copy_(u_in)
         torch.cuda.synchronize()
         e0.record(stream)
         for _ in range(args.copy_reps):
-            u_out.copy_(u_in)
+            u_cp.copy_(u_in)
         e1.record(stream)
         torch.cuda.synchronize()
+        del u_cp
         copy_ms = e0.elapsed_time(e1) / args.copy_reps
         copy_gbs = 2 * u_in.numel() * 8 / (copy_ms * 1e-3) / 1e9
         log(f"device copy of {u_in.numel() * 8 / 1e9:.2f} GB: {copy_ms * 1e3:.1f} us, {copy_gbs:.0f} GB/s")
@@ -529,7 +570,7 @@ def main():
     achieved = tile_b * count / (kernel_ms * 1e-3) / 1e9
     achieved_floor = floor_b * count / (kernel_ms * 1e-3) / 1e9
     version = hydroagg.version()
-    workload_name = f"{count}x{n}^3 F={nf}"
+    workload_name = f"{count}x{n}^3 F={nf} interior-out"
     kname = (f"hydro_lds8_kernel<{nf},{n + 2 * GHOST}>" if hydroagg.get_tile(n, nf) == 8
              else f"hydro_q4_kernel<{nf},{n + 2 * GHOST}>")
     roofline = {
@@ -550,6 +591,7 @@ def main():
         "floor_bytes_per_launch": floor_b * count,
         "measured_copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
         "fp64": measured_fp64(version, workload_name, kname, kernel_ms),
+        "access_pattern_alone": pattern,
     }
 
     learned_res = model = None
@@ -590,7 +632,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{count} sub-grids of {n}^3 (+3 ghost layers), {nf} FP64 fields, "
-                        "random smooth state, one aggregated hipGraph launch per step",
+                        "random smooth state, one aggregated hipGraph launch per step, "
+                        "updated interiors written [F][n][n][n]",
             "subgrids": count, "n": n, "nfields": nf, "dx": dx, "cfl": 0.4,
             "tile": hydroagg.get_tile(n, nf),
         },
@@ -598,9 +641,13 @@ def main():
             "value": round(cells / (each_ms * 1e-3), 1), "ms_per_step": round(each_ms, 4),
             "launches_per_step": count},
         "aggregation_speedup": None if each_ms is None else round(each_ms / ms, 2),
-        "interior_output_layout": None if interior_ms is None else {
-            "ms_per_step": round(interior_ms, 5), "value": round(cells / (interior_ms * 1e-3), 1),
-            "note": "same step and inputs, u_out in the interior-only layout (not the headline)"},
+        "stored_output_layout": None if stored_ms is None else {
+            "ms_per_step": round(stored_ms, 5), "value": round(cells / (stored_ms * 1e-3), 1),
+            "kernel_ms": round(stored_kernel_ms, 5),
+            "frac": round(tile_b * count / (stored_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "note": "same step and inputs, u_out in the stored (n+6)^3 layout of u_in with only "
+                    "the interior written: each 64-byte interior row leaves the memory sectors "
+                    "it shares with ghost cells partly written"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "uneven": uneven,

@@ -168,6 +168,24 @@ int hydro_plan_launch_graph(hydro_plan_t *plan, double dt, double dx,
 int hydro_plan_destroy(hydro_plan_t *plan);
 
 /*
+ * hydro_plan_pattern_floor -- a roofline reference, not a step: the HBM
+ * access pattern of the aggregated 8^3 step without its arithmetic, over a
+ * plan's batch (all sub-grids with n = 8 and one field count).  One launch
+ * on `stream` reads exactly the cells the step reads, in the step's order
+ * and lane roles, and writes each interior once in its descriptor's output
+ * layout; the values written are the input interior plus a negligible
+ * multiple of the ghost cells read (no physical meaning: u_out holds no step
+ * result afterwards).  same_lds != 0 reserves the step kernel's LDS, so it
+ * runs at the step's work-groups per CU; 0 lets as many run as registers
+ * allow.  Its duration is what the step's data movement alone costs
+ * (bench.py reports it beside the step's).
+ * Errors: HYDRO_EINVAL for a NULL plan or a plan with another shape or two
+ * field counts; HYDRO_EHIP if the launch fails.
+ */
+int hydro_plan_pattern_floor(hydro_plan_t *plan, int32_t same_lds,
+                             void *stream);
+
+/*
  * Bricks: a regular block of nb[0] x nb[1] x nb[2] sub-grids of one shape
  * (edge n, nfields fields, one octree level) tiling a rectangular domain of
  * n*nb[0] x n*nb[1] x n*nb[2] cells, each sub-grid stored as in hydro_step

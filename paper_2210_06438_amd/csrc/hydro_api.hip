@@ -24,6 +24,7 @@
 #include "hydro_lds8.hpp"
 #include "hydro_q4.hpp"
 #include "hydro_mixed.hpp"
+#include "hydro_pattern.hpp"
 #include "internal.hpp"
 
 using hydro::ArgDescs;
@@ -799,6 +800,33 @@ int hydro_plan_launch_graph(hydro_plan_t* p, double dt, double dx, double* amax_
     p->g_tiles = tiles;
   }
   HIP_TRY(hipGraphLaunch(p->exec, (hipStream_t)stream));
+  return HYDRO_OK;
+}
+
+int hydro_plan_pattern_floor(hydro_plan_t* p, int32_t same_lds, void* stream) {
+  g_err[0] = '\0';
+  if (!p) return fail(HYDRO_EINVAL, "plan is NULL");
+  if (p->count == 0) return HYDRO_OK;
+  int cls = -1;
+  for (int c = 0; c < kClasses; ++c)
+    if (p->num[c]) {
+      if (cls >= 0 || (c != class_of(8, 6) && c != class_of(8, 11)))
+        return fail(HYDRO_EINVAL, "the pattern kernel takes plans of n = 8 and one field count");
+      cls = c;
+    }
+  hipStream_t s = (hipStream_t)stream;
+  const dim3 grid(p->count), block(hydro::Lds8::kThreads);
+  const DevDesc* table = p->table + p->off[cls];
+  const bool f11 = cls == class_of(8, 11);
+  if (f11 && same_lds)
+    hipLaunchKernelGGL((hydro::hydro_pattern_kernel<11, true>), grid, block, 0, s, table, p->count);
+  else if (f11)
+    hipLaunchKernelGGL((hydro::hydro_pattern_kernel<11, false>), grid, block, 0, s, table, p->count);
+  else if (same_lds)
+    hipLaunchKernelGGL((hydro::hydro_pattern_kernel<6, true>), grid, block, 0, s, table, p->count);
+  else
+    hipLaunchKernelGGL((hydro::hydro_pattern_kernel<6, false>), grid, block, 0, s, table, p->count);
+  HIP_TRY(hipGetLastError());
   return HYDRO_OK;
 }
 

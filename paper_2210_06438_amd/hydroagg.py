@@ -90,6 +90,8 @@ def lib() -> ctypes.CDLL:
             f.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                           ctypes.c_void_p, ctypes.c_void_p]
             f.restype = ctypes.c_int
+        L.hydro_plan_pattern_floor.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+        L.hydro_plan_pattern_floor.restype = ctypes.c_int
         L.hydro_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), P, ctypes.c_int32]
         L.hydro_plan_create.restype = ctypes.c_int
         for name in ("hydro_plan_step", "hydro_plan_launch_graph"):
@@ -317,6 +319,11 @@ class Plan:
 
     def graph(self, dt: float, dx: float, amax=None, stream=None) -> None:
         _check(lib().hydro_plan_launch_graph(self._h, float(dt), float(dx), _ptr(amax), _stream(stream)))
+
+    def pattern_floor(self, same_lds: bool = True, stream=None) -> None:
+        """The step's HBM access pattern without its arithmetic, over this
+        plan's batch (a roofline reference; u_out receives no step result)."""
+        _check(lib().hydro_plan_pattern_floor(self._h, int(bool(same_lds)), _stream(stream)))
 
     def close(self) -> None:
         if self._h:

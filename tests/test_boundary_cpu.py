@@ -145,3 +145,8 @@ def test_brick_arguments_are_rejected_before_any_gpu_call():
         assert fn(None, 0.1, 0.1, None, None) == hydroagg.HYDRO_EINVAL
     assert L.hydro_rk3_stage(None, 1, 0.1, 0.1, None, None) == hydroagg.HYDRO_EINVAL
     assert L.hydro_rk3_destroy(None) == hydroagg.HYDRO_OK
+
+
+def test_pattern_floor_needs_a_plan():
+    L = hydroagg.lib()
+    assert L.hydro_plan_pattern_floor(None, 1, None) == hydroagg.HYDRO_EINVAL
