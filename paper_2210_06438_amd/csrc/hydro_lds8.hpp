@@ -32,8 +32,10 @@
 // Direction sums: lanes of the x and y waves add their flux differences into
 // a zeroed LDS accumulator with atomic adds -- exactly two adds onto zero per
 // cell, which is order-independent, so the result is deterministic.  Lanes of
-// the z wave keep U - lambda*dF_z and, after a barrier, write
-// U_out = (U - lambda*dF_z) - lambda*(dF_x + dF_y).
+// the z wave store U - lambda*dF_z to LDS; after a barrier every lane of the
+// work-group finishes a share of the cells,
+// U_out = (U - lambda*dF_z) - lambda*(dF_x + dF_y), so no wave carries the
+// finalization alone, and consecutive lanes store consecutive cells.
 #pragma once
 
 #include "hydro_kernel.hpp"
@@ -257,6 +259,46 @@ __device__ __forceinline__ void recon_at(Recon<K>& rc, const double (&q)[K],
   recon_step<(I < 6 ? I : 6), K>(rc, q, Wm, Wp);
 }
 
+// Finalize NFLD fields of a block from LDS, shared by all lanes of the
+// work-group (lane t takes the cells t, t + 192, ...): for every interior cell
+// the block owns, U_out = Z - lambda * (X + Y), where Z holds the z lanes'
+// U - lambda dF_z and X, Y the x and y flux differences.  Field kfirst + r
+// takes Z from zreg(r) and X + Y from its sum: the hydro core's atomically
+// accumulated acc region r (SPLIT false; X + Y = 0 + dF_x + dF_y), or the
+// passive fields' separate x (acc region r) and y (held region r)
+// differences (SPLIT true; the same value, dF_x + dF_y).  With interior-only
+// outputs of an 8^3 sub-grid the lanes of a wave store 512 contiguous bytes.
+template <int NFLD, int MP, bool SPLIT>
+__device__ __forceinline__ void finalize_shared(const double* __restrict__ held,
+                                                const double* __restrict__ acc, int kfirst,
+                                                double lambda, double* __restrict__ uout,
+                                                bool compact, long ofs, int ox, int oy, int oz,
+                                                int lox, int loy, int loz, int t) {
+  constexpr int NI = MP - 2 * kGhost;
+  constexpr int CELLS = NFLD * 512;
+  constexpr int J = (CELLS + Lds8::kThreads - 1) / Lds8::kThreads;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int e = t + j * Lds8::kThreads;
+    if (j + 1 < J || e < CELLS) {
+      const int r = e >> 9, x = e & 7, y = (e >> 3) & 7, z = (e >> 6) & 7;
+      const int lc = lcell(x, y, z);
+      double v;
+      if constexpr (SPLIT) {
+        const double* zb = r < 2 ? acc + (3 + r) * Lds8::P : held + 3 * Lds8::P;
+        v = zb[lc] - lambda * (acc[r * Lds8::P + lc] + held[r * Lds8::P + lc]);
+      } else {
+        v = held[r * Lds8::P + lc] - lambda * acc[r * Lds8::P + lc];
+      }
+      if (x >= lox && y >= loy && z >= loz) {
+        const long o = compact ? (kfirst + r) * ofs + ((long)(oz + z) * NI + oy + y) * NI + ox + x
+                               : (kfirst + r) * Frame<MP>::FS + Frame<MP>::cell(x, y, z);
+        __builtin_nontemporal_store(v, &as_global(uout)[o]);
+      }
+    }
+  }
+}
+
 // One sub-grid per work-group.  Loads are issued in two bursts: the hydro
 // core (interior shares to LDS, ghosts to registers) at the start, and all
 // passive fields together right after the hydro march, so the passive phase
@@ -300,18 +342,13 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int
   const int gstride = Frame<MP>::stride(dir);
   const double lambda = dt / ldexp(dx, -d.level);
   const double* __restrict__ uin = d.u_in + org;
-  // z lanes write column (a, b) from c = loz on, if they own (a, b).  Output
-  // element (field k, block-local z = c) of the column is
-  // uout[k * ofs + obase + c * ostride], in the stored layout of u_in or in
-  // the interior-only layout [F][n][n][n] (block origin (ox, oy, oz)).
-  const bool owner = a >= lox && b >= loy;
+  // Outputs go to the stored layout of u_in (block frame at `org`) or to the
+  // interior-only layout [F][n][n][n] (block origin (ox, oy, oz)); the cells
+  // a block owns start at (lox, loy, loz).
   constexpr int NI = MP - 2 * kGhost;
   const bool compact = d.compact != 0;
   double* __restrict__ uout = compact ? d.u_out : d.u_out + org;
   const long ofs = compact ? (long)NI * NI * NI : FS;
-  const int ostride = compact ? NI * NI : MP * MP;
-  const int obase = compact ? (oz * NI + oy + b) * NI + ox + a
-                            : Frame<MP>::line(2, a, b, kGhost);
 
   // ---- stage the hydro core ---------------------------------------------
   {
@@ -382,21 +419,10 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int
   load_share<NA, MP>(uin + 5 * FS, t, ps);
   load_ghosts<NA, MP>(uin + 5 * FS, gbase, gstride, pg);
   __syncthreads();   // hydro sums complete; tin free
-  if (dir == 2) {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-#pragma unroll
-      for (int c = 0; c < N; ++c) {
-        const int cell = k * P + lbase + c * lstride;
-        if (owner && c >= loz)
-          __builtin_nontemporal_store(held[cell] - lambda * acc[cell],
-                                      &as_global(uout)[k * ofs + obase + c * ostride]);
-        acc[cell] = 0.0;
-      }
-    }
-  }
+  finalize_shared<5, MP, false>(held, acc, 0, lambda, uout, compact, ofs, ox, oy, oz, lox, loy,
+                                loz, t);
   store_share<NA>(tin, t, ps);
-  __syncthreads();   // tin holds the first passive fields; accumulator clear
+  __syncthreads();   // tin holds the first passive fields; the hydro core is written
   // second burst, in flight during the first marches
   Share<NBs> psb;
   double pgb[NBs][6];
@@ -405,10 +431,19 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int
     load_ghosts<NB, MP>(uin + (5 + NA) * FS, gbase, gstride, pgb);
   }
 
-  // ---- passive fields, one at a time, from LDS ---------------------------
+  // ---- passive fields from LDS, in two groups of at most 3 ----------------
+  // Within a group every wave marches its direction for each field in turn,
+  // with no barrier between fields and no atomics: the x lanes store their
+  // flux differences to acc region r, the y lanes to held region r, the z
+  // lanes U - lambda dF_z to zreg(r) (acc regions 3, 4, then held region 3)
+  // for the group's r-th field; one barrier then lets every lane finalize the
+  // group.  The second burst goes to LDS (tin regions NA..) during the first
+  // group, which reads only regions 0..NA-1.
+  static_assert(NA <= 3 && NB <= 3, "passive groups of at most 3 fields");
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
-    double L[N];
+    const int r = p < NA ? p : p - NA;
+    double* const zr = r < 2 ? acc + (3 + r) * P : held + 3 * P;
     Recon<1> rc;
     double Fprev = 0.0;
     double q[1], Wm[1], Wp[1];
@@ -433,32 +468,28 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int
         const double Fh = wm[i - 5] * Wm[0] + wp[i - 5] * Wp[0];
         if (i >= 6) {
           const int cell = lbase + (i - 6) * lstride;
-          if (dir == 2)
-            L[i - 6] = tin[p * P + cell] - lambda * (Fh - Fprev);
+          if (dir == 0)
+            acc[r * P + cell] = Fh - Fprev;
+          else if (dir == 1)
+            held[r * P + cell] = Fh - Fprev;
           else
-            atomicAdd(&acc[(p % 2) * P + cell], Fh - Fprev);
+            zr[cell] = tin[p * P + cell] - lambda * (Fh - Fprev);
         }
         Fprev = Fh;
       }
     }
-    // the second burst goes to LDS before the barrier that ends field NA-1,
-    // so every later field finds it there
-    if constexpr (NB > 0) {
-      if (p == NA - 1) store_share<NB>(tin + NA * P, t, psb);
+    if (p == NA - 1) {
+      if constexpr (NB > 0) store_share<NB>(tin + NA * P, t, psb);
+      __syncthreads();
+      finalize_shared<NA, MP, true>(held, acc, 5, lambda, uout, compact, ofs, ox, oy, oz, lox,
+                                    loy, loz, t);
+      if constexpr (NB > 0) __syncthreads();   // group 1 read before group 2 writes
     }
-    // Alternate two accumulator regions: field p is finished by the z lanes
-    // after the barrier, while the x/y lanes may already add field p+1 into
-    // the other region; region p%2 is reused two fields later, after the
-    // next barrier, by which time the z lanes have cleared it.
-    __syncthreads();
-    if (dir == 2) {
-#pragma unroll
-      for (int c = 0; c < N; ++c) {
-        const int cell = (p % 2) * P + lbase + c * lstride;
-        if (owner && c >= loz)
-          __builtin_nontemporal_store(L[c] - lambda * acc[cell],
-                                      &as_global(uout)[(5 + p) * ofs + obase + c * ostride]);
-        acc[cell] = 0.0;
+    if constexpr (NB > 0) {
+      if (p == NP - 1) {
+        __syncthreads();
+        finalize_shared<NB, MP, true>(held, acc, 5 + NA, lambda, uout, compact, ofs, ox, oy, oz,
+                                      lox, loy, loz, t);
       }
     }
   }
