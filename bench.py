@@ -199,6 +199,98 @@ def timestep_leg(args, torch, hydroagg, workloads, dev, stream):
                              "and CPU work included there, device kernels only here"}
 
 
+def strategies_leg(args, torch, hydroagg, workloads, dev, stream):
+    """The paper's three aggregation strategies on this GPU (Section V, the
+    parameter grid of Table III), on its scenario shape (Table II: 512
+    sub-grids of 8^3, or 64 of 16^3 with the same cells), F = 11.  A
+    time-step is three iterations; an iteration steps every sub-grid once.
+    Strategy 1: 16^3 sub-grids, one launch each.  Strategy 2: 8^3 sub-grids,
+    one launch each, dealt over k streams.  Strategy 3: the aggregator with
+    max width W on one stream, every iteration's tasks arriving as a burst
+    (aggregated while the stream is busy).  2+3: the aggregator with W and k
+    streams.  Host wall time per time-step, median of --strategy-reps."""
+    nf, dt, dx = args.nfields, 2e-3, 1.0 / 64
+    u8 = torch.from_numpy(workloads.random_smooth(512, n=8, nfields=nf, seed=9)).to(dev)
+    o8 = torch.empty((512, nf, 8, 8, 8), dtype=torch.float64, device=dev)
+    u16 = torch.from_numpy(workloads.random_smooth(64, n=16, nfields=nf, seed=10)).to(dev)
+    o16 = torch.empty((64, nf, 16, 16, 16), dtype=torch.float64, device=dev)
+    d8 = hydroagg.subgrids(u8, o8)
+    d16 = hydroagg.subgrids(u16, o16)
+    cells = 512 * 8 ** 3
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.strategy_reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return round(statistics.median(ts), 3)
+
+    def iters(step):
+        def run():
+            for _ in range(3):
+                step()
+        return run
+
+    rows = []
+    ms = timed(iters(lambda: hydroagg.hydro_step_each(d16, dt, dx, None, stream)))
+    rows.append({"strategy": "1", "subgrid": "16^3", "executors": 1, "max_aggregated": 1,
+                 "ms_per_timestep": ms})
+    hydroagg.hydro_step_streams(d8, dt, dx, None, n_streams=max(args.strategy_streams), stream=stream)
+    for k in args.strategy_streams:
+        ms = timed(iters(lambda: hydroagg.hydro_step_streams(d8, dt, dx, None, n_streams=k,
+                                                             stream=stream)))
+        rows.append({"strategy": "2", "subgrid": "8^3", "executors": k, "max_aggregated": 1,
+                     "ms_per_timestep": ms})
+
+    def agg_row(label, width, k):
+        agg = hydroagg.Aggregator(width, timeout_us=-1.0, n_streams=k, flush_when_idle=True)
+
+        def it():
+            agg.submit_many(d8, dt, dx)
+            agg.drain()
+        ms = timed(iters(it))
+        st = agg.stats()
+        agg.close()
+        rows.append({"strategy": label, "subgrid": "8^3", "executors": k, "max_aggregated": width,
+                     "ms_per_timestep": ms,
+                     "mean_batch": round(st["launched"] / max(st["batches"], 1), 2)})
+
+    for w in args.strategy_widths:
+        agg_row("3", w, 1)
+    for k, w in args.strategy_combos:
+        agg_row("2+3", w, k)
+    ms = timed(iters(lambda: hydroagg.hydro_step(d8, dt, dx, None, stream)))
+    rows.append({"strategy": "one launch per iteration", "subgrid": "8^3", "executors": 1,
+                 "max_aggregated": 512, "ms_per_timestep": ms})
+    for r in rows:
+        r["cell_updates_per_s"] = round(3 * cells / (r["ms_per_timestep"] * 1e-3), 1)
+        log(f"strategy {r['strategy']}: {r['subgrid']}, {r['executors']} executors, max "
+            f"aggregated {r['max_aggregated']}: {r['ms_per_timestep']} ms per time-step")
+    base = next(r for r in rows if r["strategy"] == "2" and r["executors"] == 1)["ms_per_timestep"]
+    s2 = [r for r in rows if r["strategy"] == "2"]
+    s2_best = min(r["ms_per_timestep"] for r in s2)
+    s2_max = max(s2, key=lambda r: r["executors"])["ms_per_timestep"]
+    agg_rows = [r for r in rows if r["strategy"] in ("3", "2+3")]
+    best = min(agg_rows, key=lambda r: r["ms_per_timestep"])
+    return {"workload": "512 sub-grids of 8^3 (64 of 16^3 for strategy 1), 11 FP64 fields, "
+                        "random smooth state, 3 iterations per time-step",
+            "rows": rows,
+            "best_aggregated": {k: best[k] for k in ("strategy", "executors", "max_aggregated",
+                                                     "ms_per_timestep")},
+            "speedup_best_vs_non_aggregated": round(base / best["ms_per_timestep"], 2),
+            "speedup_best_vs_strategy2_most_streams": round(s2_max / best["ms_per_timestep"], 2),
+            "speedup_best_vs_strategy2_best": round(s2_best / best["ms_per_timestep"], 2),
+            "paper_context": "MI100 with HIP kernels (Table III): 1404 ms non-aggregated, 584 ms "
+                             "with 128 executors, 166 ms strategy 3 (max 128), 130 ms best "
+                             "combination (128 executors, max 16); 10.80x and 4.49x. Whole "
+                             "application time per time-step there (5 kernels per sub-grid per "
+                             "iteration, transfers, CPU work), the hydro kernel alone here"}
+
+
 def _time_oracle(oracle, U, dt, dx, threads, seconds, levels=None, reps=2):
     """Median wall time of oracle.step over repetitions lasting >= seconds."""
     times = []
@@ -412,6 +504,15 @@ def main():
                     help="1: also time the step's access pattern without its arithmetic")
     ap.add_argument("--learned-splits", type=int, default=10)
     ap.add_argument("--no-timestep", action="store_true", help="skip the SSP-RK3 time-step leg")
+    ap.add_argument("--no-strategies", action="store_true", help="skip the strategy comparison leg")
+    ap.add_argument("--strategy-reps", type=int, default=3)
+    ap.add_argument("--strategy-streams", type=int, nargs="*",
+                    default=[1, 2, 4, 8, 16, 32, 64, 128])
+    ap.add_argument("--strategy-widths", type=int, nargs="*",
+                    default=[1, 2, 4, 8, 16, 32, 64, 128])
+    ap.add_argument("--strategy-combos", type=lambda v: tuple(int(x) for x in v.split("x")),
+                    nargs="*", default=[(64, 8), (128, 8), (128, 16), (128, 32), (4, 16), (8, 32)],
+                    help="streams x width pairs of the 2+3 combination, e.g. 128x16")
     ap.add_argument("--timestep-steps", type=int, default=50)
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads (0 = OMP_NUM_THREADS or all cores)")
@@ -613,6 +714,10 @@ def main():
     if not args.no_timestep:
         timestep = timestep_leg(args, torch, hydroagg, workloads, dev, stream)
 
+    strategies = None
+    if not args.no_strategies:
+        strategies = strategies_leg(args, torch, hydroagg, workloads, dev, stream)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_leg(args, U, dt, dx, cells, poly)
@@ -654,6 +759,7 @@ def main():
         "serving": serving,
         "learned_width": learned_res,
         "timestep": timestep,
+        "strategies": strategies,
         "tile_autotune": tiles,
     }
     plan.close()

@@ -133,6 +133,23 @@ int hydro_step_static(const hydro_subgrid_t *sg, int32_t count, double dt,
                       double dx, double *amax_dev, void *stream);
 
 /*
+ * hydro_step_streams -- the paper's strategy 2 (Section V-C, implicit work
+ * aggregation): the same kernel launched once per sub-grid, the launches
+ * dealt round-robin to n_streams (1..128) library-owned streams, so that
+ * the GPU may run the small kernels side by side.  The pool streams start
+ * after the work already queued on `stream` and `stream` continues after
+ * all of them (an event each way), so the call is ordered on `stream` like
+ * hydro_step.  The pool's streams are created at first use, up to the
+ * largest n_streams asked for, and kept until the process ends; a call with
+ * count = 0 only creates them (set-up).  Calls are serialised by a mutex per
+ * device.  Results, amax and errors as hydro_step (results bitwise equal to
+ * it); HYDRO_EINVAL for n_streams outside 1..128.
+ */
+int hydro_step_streams(const hydro_subgrid_t *sg, int32_t count, double dt,
+                       double dx, double *amax_dev, int32_t n_streams,
+                       void *stream);
+
+/*
  * hydro_step_each -- the non-aggregated baseline: the same kernel launched
  * once per sub-grid (the paper's "1 executor, max aggregated 1" setting,
  * Section VI-B), every launch on `stream`, each carrying its one descriptor
@@ -272,7 +289,7 @@ int hydro_rk3_destroy(hydro_rk3_t *rk);
  * Admission is bounded: held plus in-flight tasks may not own more than
  * hbm_budget_bytes of output (0 = unbounded); hydro_submit then returns
  * HYDRO_EAGAIN and the caller retries after hydro_progress / completions.
- * n_streams (1..8) streams and all batch buffers are created by
+ * n_streams (1..128) streams and all batch buffers are created by
  * hydro_agg_create; submit/flush/progress/poll never allocate.  Calls on one
  * aggregator are serialised by an internal mutex.  If a launch that
  * hydro_submit triggers fails (HYDRO_EHIP), the task stays held with its
@@ -296,6 +313,20 @@ int hydro_agg_create(hydro_agg_t **out, int32_t max_width, double timeout_us,
                      int32_t flush_when_idle);
 int hydro_submit(hydro_agg_t *agg, const hydro_subgrid_t *sg, double dt,
                  double dx, uint64_t *ticket);
+/* hydro_submit_many: count tasks submitted in order, exactly as count
+ * hydro_submit calls would be (each may trigger a launch by the rules above;
+ * this is how a burst of tasks reaches the aggregator without a host call
+ * per task).  tickets: count uint64_t, or NULL for fire-and-forget tasks
+ * whose completion records are dropped when their batch completes (their
+ * tickets are unknown to poll/wait; use hydro_agg_drain).  *submitted
+ * receives the number of tasks taken; HYDRO_EAGAIN when admission stops the
+ * burst (the rest were not submitted).  Errors as hydro_submit. */
+int hydro_submit_many(hydro_agg_t *agg, const hydro_subgrid_t *sg,
+                      int32_t count, double dt, double dx, uint64_t *tickets,
+                      int32_t *submitted);
+/* hydro_agg_drain: launch whatever is held and wait for every batch in
+ * flight (results of tasks with tickets stay retrievable). */
+int hydro_agg_drain(hydro_agg_t *agg);
 int hydro_flush(hydro_agg_t *agg);     /* launch whatever is held now        */
 int hydro_progress(hydro_agg_t *agg);  /* collect completions; apply the
                                           timeout / idle-stream rules        */

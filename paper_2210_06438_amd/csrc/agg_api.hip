@@ -43,6 +43,9 @@ struct SteadyClock {
   }
 };
 
+// The most streams of one aggregator (the paper's largest executor count).
+constexpr int kAggMaxStreams = 128;
+
 // Executor on HIP streams.
 class HipExec {
  public:
@@ -280,10 +283,10 @@ class HipExec {
 
   int ns_ = 0, created_ = 0, cap_ = 0;
   double launch_us_ = 0.0;
-  hipStream_t streams_[8] = {};
+  hipStream_t streams_[kAggMaxStreams] = {};
   std::vector<Slot> slots_;
   uint64_t* flags_ = nullptr;   // pinned; flags_[k] = id of the last finished batch of slot k
-  uint64_t last_[8] = {};       // newest batch launched on each stream
+  uint64_t last_[kAggMaxStreams] = {};  // newest batch launched on each stream
   std::unordered_map<uint64_t, int> live_;
   std::deque<uint64_t> order_;
   std::unordered_map<uint64_t, std::vector<double>> retired_;
@@ -317,11 +320,15 @@ int hydro_agg_create(hydro_agg_t** out, int32_t max_width, double timeout_us,
   if (!out) return fail(HYDRO_EINVAL, "out is NULL");
   *out = nullptr;
   if (max_width < 1 || max_width > 65536) return fail(HYDRO_EINVAL, "max_width %d", max_width);
-  if (n_streams < 1 || n_streams > 8) return fail(HYDRO_EINVAL, "n_streams %d", n_streams);
+  if (n_streams < 1 || n_streams > kAggMaxStreams)
+    return fail(HYDRO_EINVAL, "n_streams %d", n_streams);
   if (timeout_us != timeout_us) return fail(HYDRO_EINVAL, "timeout is NaN");
   hydro_agg* a = new hydro_agg();
   a->width = max_width;
-  int rc = a->ex.init(n_streams, max_width, 32);
+  // batch slots (in-flight batches): 32 per stream up to 8 streams, then
+  // 256 in all, at least 4 per stream
+  const int per_stream = n_streams <= 8 ? 32 : std::max(4, 256 / n_streams);
+  int rc = a->ex.init(n_streams, max_width, per_stream);
   if (rc) {
     a->ex.teardown();
     delete a;
@@ -350,6 +357,40 @@ int hydro_submit(hydro_agg_t* a, const hydro_subgrid_t* sg, double dt, double dx
   rc = a->pol->submit(t, dt, dx, ticket);
   if (rc == HYDRO_EAGAIN) return fail(HYDRO_EAGAIN, "admission refused: byte budget in use");
   return rc;
+}
+
+int hydro_submit_many(hydro_agg_t* a, const hydro_subgrid_t* sg, int32_t count, double dt,
+                      double dx, uint64_t* tickets, int32_t* submitted) {
+  hydro::api::clear_error();
+  if (!a || !submitted) return fail(HYDRO_EINVAL, "NULL aggregator or count out-pointer");
+  *submitted = 0;
+  int rc = hydro::api::validate_batch(sg, count, dt, dx);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(a->mu);
+  for (int32_t i = 0; i < count; ++i) {
+    Task t;
+    t.u_in = sg[i].u_in;
+    t.u_out = sg[i].u_out;
+    t.n = sg[i].n;
+    t.nfields = sg[i].nfields;
+    t.level = sg[i].level;
+    t.out_layout = sg[i].out_layout;
+    t.bytes = task_bytes(sg[i]);
+    uint64_t ticket = 0;
+    rc = a->pol->submit(t, dt, dx, &ticket, tickets == nullptr);
+    if (rc == HYDRO_EAGAIN) return fail(HYDRO_EAGAIN, "admission refused after %d tasks", i);
+    if (rc) return rc;
+    if (tickets) tickets[i] = ticket;
+    *submitted = i + 1;
+  }
+  return HYDRO_OK;
+}
+
+int hydro_agg_drain(hydro_agg_t* a) {
+  hydro::api::clear_error();
+  if (!a) return fail(HYDRO_EINVAL, "NULL aggregator");
+  std::lock_guard<std::mutex> lk(a->mu);
+  return a->pol->drain();
 }
 
 int hydro_flush(hydro_agg_t* a) {

@@ -67,8 +67,11 @@ class AggPolicy {
       : ex_(ex), clk_(clk), W_(max_width), timeout_(timeout_us), budget_(budget),
         idle_flush_(flush_when_idle) {}
 
-  // Queue one task; may launch.  Returns 0, HYDRO-style negative codes.
-  int submit(const Task& t_in, double dt, double dx, uint64_t* ticket) {
+  // Queue one task; may launch.  Returns 0, HYDRO-style negative codes.  A
+  // task submitted with `forget` keeps no completion record: its ticket is
+  // unknown once its batch has been collected (fire-and-forget tasks whose
+  // completion the caller learns from drain()).
+  int submit(const Task& t_in, double dt, double dx, uint64_t* ticket, bool forget = false) {
     if (!pending_.empty() && (dt != dt_ || dx != dx_)) {
       int rc = launch_pending(kParam);
       if (rc) return rc;
@@ -86,7 +89,7 @@ class AggPolicy {
     }
     pending_.push_back(t);
     held_bytes_ += t.bytes;
-    state_[t.ticket] = Where{kPendingBatch, 0};
+    state_[t.ticket] = Where{kPendingBatch, 0, 0.0, forget};
     stats_.submitted++;
     *ticket = t.ticket;
     if ((int)pending_.size() >= W_) return launch_pending(kWidth);
@@ -176,6 +179,7 @@ class AggPolicy {
     Kind kind;
     uint64_t batch;
     double amax = 0.0;
+    bool forget = false;
   };
   struct Batch {
     uint64_t batch;
@@ -207,7 +211,9 @@ class AggPolicy {
     for (const Task& t : pending_) {
       rec.tickets.push_back(t.ticket);
       rec.bytes += t.bytes;
-      state_[t.ticket] = Where{kInFlight, b};
+      Where& w = state_[t.ticket];
+      w.kind = kInFlight;
+      w.batch = b;
     }
     const int w = (int)pending_.size();
     int bin = 0;
@@ -231,11 +237,12 @@ class AggPolicy {
     // Batches on one stream finish in order, across streams in any order:
     // once a batch is found unfinished, later batches of its stream are not
     // polled.
-    uint32_t blocked = 0;
+    uint64_t blocked[2] = {0, 0};   // streams 0..127
     for (auto it = inflight_.begin(); it != inflight_.end();) {
-      const uint32_t bit = 1u << (it->stream & 31);
-      if ((blocked & bit) || !ex_.done(it->batch)) {
-        blocked |= bit;
+      const int sb = it->stream & 127;
+      const uint64_t bit = 1ull << (sb & 63);
+      if ((blocked[sb >> 6] & bit) || !ex_.done(it->batch)) {
+        blocked[sb >> 6] |= bit;
         ++it;
         continue;
       }
@@ -243,6 +250,10 @@ class AggPolicy {
       ex_.results(it->batch, amax_buf_.data());
       for (size_t i = 0; i < it->tickets.size(); ++i) {
         auto st = state_.find(it->tickets[i]);
+        if (st != state_.end() && st->second.forget) {
+          state_.erase(st);
+          continue;
+        }
         if (st != state_.end()) st->second = Where{kDone, it->batch, amax_buf_[i]};
         if (record_) completed_.emplace_back(it->tickets[i], amax_buf_[i]);
       }

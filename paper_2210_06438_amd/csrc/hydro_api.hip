@@ -375,6 +375,31 @@ int step_chunk(DeviceState* st, const FixedTable* fixed, const hydro_subgrid_t* 
   return release_table(t, stream);
 }
 
+// ---- strategy 2: one launch per sub-grid over a pool of streams -----------
+// The pool's streams (the paper's GPU executors, Section V-C) are created at
+// first use, up to the largest count asked for, and kept until the process
+// ends: creating a stream is set-up, not step work.
+constexpr int kPoolMax = 128;
+
+struct StreamPool {
+  std::mutex mu;
+  int created = 0;
+  hipStream_t s[kPoolMax] = {};
+  hipEvent_t done[kPoolMax] = {};
+  hipEvent_t fork = nullptr;
+};
+StreamPool g_pool[kMaxDevices];
+
+int pool_reserve(StreamPool& p, int k) {
+  if (!p.fork) HIP_TRY(hipEventCreateWithFlags(&p.fork, hipEventDisableTiming));
+  while (p.created < k) {
+    HIP_TRY(hipStreamCreateWithFlags(&p.s[p.created], hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&p.done[p.created], hipEventDisableTiming));
+    ++p.created;
+  }
+  return HYDRO_OK;
+}
+
 // ---- allocation-free step (hydro_step_static) ----------------------------
 // The descriptor table of hydro_step_static lives in `scratch`, a static
 // device array (each GPU holds its own copy at its own address), and its host
@@ -684,6 +709,40 @@ int hydro_step_static(const hydro_subgrid_t* sg, int32_t count, double dt, doubl
   }
   const FixedTable fixed{st.host, st.dev};
   return step_chunk(nullptr, &fixed, sg, count, 0, dt, dx, amax_dev, (hipStream_t)stream);
+}
+
+int hydro_step_streams(const hydro_subgrid_t* sg, int32_t count, double dt, double dx,
+                       double* amax_dev, int32_t n_streams, void* stream) {
+  g_err[0] = '\0';
+  int rc = validate(sg, count, dt, dx);
+  if (rc) return rc;
+  if (n_streams < 1 || n_streams > kPoolMax)
+    return fail(HYDRO_EINVAL, "n_streams %d outside 1..%d", n_streams, kPoolMax);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HYDRO_EINVAL, "device %d out of range", dev);
+  StreamPool& p = g_pool[dev];
+  std::lock_guard<std::mutex> lk(p.mu);
+  rc = pool_reserve(p, n_streams);
+  if (rc || count == 0) return rc;
+  hipStream_t caller = (hipStream_t)stream;
+  const int k = n_streams < count ? n_streams : count;
+  // the pool's streams start after the work already queued on `stream` ...
+  HIP_TRY(hipEventRecord(p.fork, caller));
+  for (int j = 0; j < k; ++j) HIP_TRY(hipStreamWaitEvent(p.s[j], p.fork, 0));
+  for (int i = 0; i < count; ++i) {
+    ArgDescs a;
+    memset(&a, 0, sizeof a);
+    a.d[0] = to_dev(sg[i], i);
+    rc = dispatch_args(class_of(sg[i].n, sg[i].nfields), a, 1, dt, dx, amax_dev, p.s[i % k]);
+    if (rc) return rc;
+  }
+  // ... and `stream` continues after all of them
+  for (int j = 0; j < k; ++j) {
+    HIP_TRY(hipEventRecord(p.done[j], p.s[j]));
+    HIP_TRY(hipStreamWaitEvent(caller, p.done[j], 0));
+  }
+  return HYDRO_OK;
 }
 
 int hydro_step_each(const hydro_subgrid_t* sg, int32_t count, double dt,

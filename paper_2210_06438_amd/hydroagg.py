@@ -105,6 +105,11 @@ def lib() -> ctypes.CDLL:
         L.hydro_agg_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_double,
                                        ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32]
         L.hydro_submit.argtypes = [AP, P, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]
+        L.hydro_submit_many.argtypes = [AP, P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]
+        L.hydro_agg_drain.argtypes = [AP]
+        L.hydro_step_streams.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
         L.hydro_flush.argtypes = [AP]
         L.hydro_progress.argtypes = [AP]
         L.hydro_poll.argtypes = [AP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
@@ -118,7 +123,8 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(hydro_serve_stats_t)]
         for name in ("hydro_agg_create", "hydro_submit", "hydro_flush", "hydro_progress",
                      "hydro_poll", "hydro_wait", "hydro_agg_stats", "hydro_agg_destroy",
-                     "hydro_serve_run"):
+                     "hydro_serve_run", "hydro_submit_many", "hydro_agg_drain",
+                     "hydro_step_streams"):
             getattr(L, name).restype = ctypes.c_int
         L.hydro_set_tile.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.hydro_set_tile.restype = ctypes.c_int
@@ -234,6 +240,14 @@ def hydro_step_static(descs, dt: float, dx: float, amax=None, stream=None) -> No
     nothing; at most STATIC_MAX sub-grids; overlapping calls on one GPU race)."""
     arr, count = descs
     _check(lib().hydro_step_static(arr, count, float(dt), float(dx), _ptr(amax), _stream(stream)))
+
+
+def hydro_step_streams(descs, dt: float, dx: float, amax=None, n_streams: int = 1,
+                       stream=None) -> None:
+    """Strategy 2: one launch per sub-grid over n_streams pool streams."""
+    arr, count = descs
+    _check(lib().hydro_step_streams(arr, count, float(dt), float(dx), _ptr(amax), int(n_streams),
+                                    _stream(stream)))
 
 
 def hydro_step_each(descs, dt: float, dx: float, amax=None, stream=None) -> None:
@@ -365,6 +379,22 @@ class Aggregator:
             return None
         _check(rc)
         return int(t.value)
+
+    def submit_many(self, descs, dt: float, dx: float, tickets: bool = False):
+        """Submit a batch of tasks in order, as single submits would be
+        (hydro_submit_many).  Returns the tickets as a numpy array, or None
+        for fire-and-forget tasks (tickets=False; use drain())."""
+        import numpy as np
+        arr, count = descs
+        t = np.zeros(max(count, 1), dtype=np.uint64) if tickets else None
+        done = ctypes.c_int32()
+        _check(lib().hydro_submit_many(self._h, arr, count, float(dt), float(dx),
+                                       None if t is None else t.ctypes.data, ctypes.byref(done)))
+        return None if t is None else t[:count]
+
+    def drain(self) -> None:
+        """Launch what is held and wait for everything in flight."""
+        _check(lib().hydro_agg_drain(self._h))
 
     def flush(self) -> None:
         _check(lib().hydro_flush(self._h))

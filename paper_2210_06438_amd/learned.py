@@ -12,7 +12,11 @@ width, while its magnitude (up to seconds) would otherwise dominate the
 squared error; plus the throughput deficit log(rate / throughput), which
 still ranks the widths that cannot keep up.
 The chosen width of a condition is the argmin of the prediction over the
-candidate widths; the exhaustive tuner (tune.py) is its fallback and judge.
+candidate widths.  The exhaustive tuner (tune.py) is its judge and fallback
+(JudgedWidth): the model's width is run once, and only if that run falls
+behind the offered rate -- the case in which a wrong width costs most, since
+p99 then grows with the length of the run -- or the rate lies outside the
+trained range is every candidate width run and the best one taken.
 
 Sweeps stored under data/ (made by tune.py on one MI355X):
   width_sweep_timeout.json       launch on width or 50 us timeout only (420 records)
@@ -195,6 +199,46 @@ def split(records, test_frac=0.2, seed=5):
     return train, test
 
 
+def saturated(record, slack=DRAIN_SLACK):
+    """True when a serving run fell behind its offered rate: throughput
+    deficit log(rate / throughput) beyond the drain slack."""
+    return math.log(record["rate"] / max(record["throughput"], 1e-9)) > slack
+
+
+class JudgedWidth:
+    """The width model with the exhaustive tuner as its judge and fallback.
+
+    choose(n, nfields, rate, measure) -> (width, runs, how).  measure(width)
+    serves the condition at that width once and returns its record (p99_us,
+    throughput, rate): a short serving run online, a lookup in a stored sweep
+    offline.  The model's width is measured once (runs = 1); if the run is
+    saturated (saturated()) every candidate width is measured and the lowest
+    p99 taken (runs = 1 + len(widths), how = "fallback_saturated").  A rate
+    outside the rates the model was trained on goes to the exhaustive tuner
+    directly (runs = len(widths), how = "fallback_rate")."""
+
+    def __init__(self, model, widths=WIDTHS):
+        self.model = model
+        self.widths = list(widths)
+
+    def _exhaustive(self, measure):
+        recs = [measure(w) for w in self.widths]
+        best = min(recs, key=lambda r: (r["p99_us"], r["width"]))
+        return int(best["width"]), len(recs)
+
+    def choose(self, n, nfields, rate, measure, mix=None):
+        lo, hi = self.model.rate_range
+        if not lo <= rate <= hi:
+            w, runs = self._exhaustive(measure)
+            return w, runs, "fallback_rate"
+        w = self.model.choose_mix(mix, nfields, rate, self.widths) if mix else \
+            self.model.choose(n, nfields, rate, self.widths)
+        if not saturated(measure(w)):
+            return w, 1, "model"
+        w, runs = self._exhaustive(measure)
+        return w, runs + 1, "fallback_saturated"
+
+
 class WidthModel:
     """Standardisation + MLP + argmin over candidate widths."""
 
@@ -208,6 +252,8 @@ class WidthModel:
         X = features([r["n"] for r in records], [r["nfields"] for r in records],
                      [r["rate"] for r in records], [r["width"] for r in records])
         y = target(records, self.overload_us)
+        rates = [r["rate"] for r in records]
+        self.rate_range = (min(rates), max(rates))
         self.xm, self.xs = X.mean(0), X.std(0) + 1e-12
         self.ym, self.ys = y.mean(), y.std() + 1e-12
         self.mlp = MLP(seed=self.seed, device=self.device)
@@ -250,20 +296,34 @@ def in_groups(records, gs):
     return [r for r in records if (r["n"], r["nfields"], r["rate"]) in gs]
 
 
+def sweep_measure(records, group):
+    """measure(width) for JudgedWidth offline: the stored run of the group at
+    that width (the measurement the tuner would make)."""
+    by = {r["width"]: r for r in records if (r["n"], r["nfields"], r["rate"]) == group}
+    return lambda w: by[w]
+
+
 def evaluate(records, model, test_groups, static_width):
     rows = []
+    judge = JudgedWidth(model)
     for g in test_groups:
         w = model.choose(*g)
+        jw, runs, how = judge.choose(*g, measure=sweep_measure(records, g))
         best = best_width([r for r in records if (r["n"], r["nfields"], r["rate"]) == g])[g]
         rows.append({"group": list(g), "mlp_width": w, "best_width": best[0],
                      "mlp_regret": regret(records, g, w),
+                     "judged_width": jw, "judged_regret": regret(records, g, jw),
+                     "judged_runs": runs, "judged_how": how,
                      "static_regret": regret(records, g, static_width)})
     return {"static_width": static_width, "rows": rows,
             "mlp_mean_regret": float(np.mean([r["mlp_regret"] for r in rows])),
+            "judged_mean_regret": float(np.mean([r["judged_regret"] for r in rows])),
             "static_mean_regret": float(np.mean([r["static_regret"] for r in rows])),
             "mlp_median_regret": float(np.median([r["mlp_regret"] for r in rows])),
+            "judged_median_regret": float(np.median([r["judged_regret"] for r in rows])),
             "static_median_regret": float(np.median([r["static_regret"] for r in rows])),
-            "exhaustive_runs_per_condition": len(WIDTHS), "mlp_runs_per_condition": 0}
+            "exhaustive_runs_per_condition": len(WIDTHS), "mlp_runs_per_condition": 0,
+            "judged_runs_per_condition": float(np.mean([r["judged_runs"] for r in rows]))}
 
 
 def cross_validate(records, splits=range(10), epochs=2000, lr=1e-3, model_seed=0,
@@ -283,7 +343,13 @@ def cross_validate(records, splits=range(10), epochs=2000, lr=1e-3, model_seed=0
     allrows = [r for e in out for r in e["rows"]]
     return {"splits": out,
             "mlp_mean_regret": float(np.mean([e["mlp_mean_regret"] for e in out])),
+            "judged_mean_regret": float(np.mean([e["judged_mean_regret"] for e in out])),
             "static_mean_regret": float(np.mean([e["static_mean_regret"] for e in out])),
             "mlp_median_regret": float(np.median([r["mlp_regret"] for r in allrows])),
+            "judged_median_regret": float(np.median([r["judged_regret"] for r in allrows])),
             "static_median_regret": float(np.median([r["static_regret"] for r in allrows])),
-            "mlp_wins": int(sum(e["mlp_mean_regret"] < e["static_mean_regret"] for e in out))}
+            "mlp_wins": int(sum(e["mlp_mean_regret"] < e["static_mean_regret"] for e in out)),
+            "judged_wins": int(sum(e["judged_mean_regret"] < e["static_mean_regret"] for e in out)),
+            "judged_runs_per_condition": float(np.mean([r["judged_runs"] for r in allrows])),
+            "judged_fallbacks": int(sum(r["judged_how"] != "model" for r in allrows)),
+            "conditions": len(allrows)}

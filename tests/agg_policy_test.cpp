@@ -229,7 +229,42 @@ static void completion_queue() {
   for (int i = 0; i < 4; ++i) CHECK(done[i].first == t[i] && done[i].second == 10 + i + 0.5);
 }
 
+// Fire-and-forget tasks keep no completion record once their batch is
+// collected; tasks with tickets beside them are unaffected.  Streams beyond
+// 32 (up to 128) are tracked separately when collecting.
+static void forget_and_many_streams() {
+  FakeExec ex;
+  ex.ns = 40;
+  VClock clk;
+  P p(ex, clk, 2, -1.0, 0, false);
+  uint64_t f[4], k;
+  for (int i = 0; i < 4; ++i) CHECK(p.submit(task(i), 0.1, 1.0, &f[i], true) == 0);
+  CHECK(p.submit(task(7), 0.1, 1.0, &k) == 0);
+  CHECK(p.flush() == 0);
+  CHECK(ex.order.size() == 3);   // widths 2, 2, 1 on streams 0, 1, 2
+  int done = 0;
+  double am = 0;
+  CHECK(p.poll(f[0], &done, &am) == 0 && done == 0);   // still in flight: known
+  CHECK(p.drain() == 0);
+  for (int i = 0; i < 4; ++i) CHECK(p.poll(f[i], &done, &am) == -1);   // dropped
+  CHECK(p.poll(k, &done, &am) == 0 && done == 1 && am == 7.5);
+  CHECK(p.quiescent());
+  // batches on streams 0 and 32 (same bit in a 32-bit mask): completing the
+  // one on stream 32 must be collected while stream 0's is still running
+  FakeExec ex2;
+  ex2.ns = 40;
+  VClock clk2;
+  P q(ex2, clk2, 1, -1.0, 0, false);
+  uint64_t t[40];
+  for (int i = 0; i < 33; ++i) CHECK(q.submit(task(i), 0.1, 1.0, &t[i]) == 0);   // width 1
+  CHECK(ex2.order.size() == 33 && ex2.b.at(ex2.order[32]).stream == 32);
+  ex2.b.at(ex2.order[32]).done = true;
+  CHECK(q.poll(t[32], &done, &am) == 0 && done == 1 && am == 32.5);
+  CHECK(q.poll(t[0], &done, &am) == 0 && done == 0);
+}
+
 int main() {
+  forget_and_many_streams();
   width_rule();
   idle_rule();
   timeout_rule();

@@ -150,3 +150,17 @@ def test_brick_arguments_are_rejected_before_any_gpu_call():
 def test_pattern_floor_needs_a_plan():
     L = hydroagg.lib()
     assert L.hydro_plan_pattern_floor(None, 1, None) == hydroagg.HYDRO_EINVAL
+
+
+def test_strategy_and_bulk_calls_check_arguments():
+    L = hydroagg.lib()
+    for k in (0, -1, 129):
+        assert L.hydro_step_streams(_desc(), 1, 0.1, 0.1, None, k, None) == hydroagg.HYDRO_EINVAL
+    assert L.hydro_step_streams(_desc(n=9), 1, 0.1, 0.1, None, 4, None) == hydroagg.HYDRO_EINVAL
+    n = ctypes.c_int32()
+    assert L.hydro_submit_many(None, _desc(), 1, 0.1, 0.1, None, ctypes.byref(n)) == \
+        hydroagg.HYDRO_EINVAL
+    assert L.hydro_agg_drain(None) == hydroagg.HYDRO_EINVAL
+    h = ctypes.c_void_p()
+    for k in (0, 129):
+        assert L.hydro_agg_create(ctypes.byref(h), 4, 50.0, k, 0, 1) == hydroagg.HYDRO_EINVAL

@@ -100,7 +100,7 @@ def test_aggregator_errors(dev):
     with pytest.raises(hydroagg.HydroError):
         hydroagg.Aggregator(0)
     with pytest.raises(hydroagg.HydroError):
-        hydroagg.Aggregator(4, n_streams=9)
+        hydroagg.Aggregator(4, n_streams=129)
     agg = hydroagg.Aggregator(4)
     with pytest.raises(hydroagg.HydroError):
         agg.poll(12345)
