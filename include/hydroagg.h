@@ -279,6 +279,106 @@ int hydro_rk3_launch_graph(hydro_rk3_t *rk, double dt, double dx,
 int hydro_rk3_destroy(hydro_rk3_t *rk);
 
 /*
+ * Aggregation regions: the paper's application-independent aggregation
+ * executor (Section V-D).  A region is a piece of task code -- staging
+ * buffers, filling them, copies, a kernel launch -- that several tasks (host
+ * threads) may run together as one team, each on its own chunk of shared
+ * buffers, the GPU work issued once for the whole team:
+ *   hydro_region_enter   blocks until the task enters with a team: at once
+ *                        (with whoever waits) when one of the region's
+ *                        n_streams executors is idle, else when max_team
+ *                        tasks wait (that full team enters anyway and queues
+ *                        behind the team on an executor; two team slots per
+ *                        executor), else when an executor frees.  *task
+ *                        receives its team, index (0..size-1) and size.
+ *   hydro_region_alloc   the k-th call of every member is one team buffer:
+ *                        the first member reserves size x stride bytes
+ *                        (stride = bytes rounded up to 8) of the team's
+ *                        arena; each member gets its chunk (host mirror and
+ *                        device address) at index x stride.  Every member
+ *                        must ask for the same bytes.
+ *   hydro_region_buffer  device base address and stride of a team buffer
+ *                        (for kernel arguments).
+ *   hydro_region_upload / _download  host mirror to device / back, of a
+ *                        whole team buffer, once, when the last member calls.
+ *   hydro_region_launch  `kernel` (a __global__ function of this library,
+ *                        hydro_region_kernel(), or of the caller's code) runs
+ *                        once, when the last member calls, with size x
+ *                        blocks_per_task work-groups of `threads` lanes and
+ *                        the last caller's `args` (hipLaunchKernel style: an
+ *                        array of pointers to each argument); the kernel finds
+ *                        its member from its work-group index.
+ *   hydro_region_leave   the last member records the team's completion;
+ *                        every member returns when the team's device work has
+ *                        finished (its downloaded chunks are then valid).
+ * Every member makes the same sequence of calls ("single GPU workload,
+ * multiple tasks"); a call that differs from the team's (kind, bytes,
+ * launch shape) fails the team with HYDRO_EINVAL, an arena overflow with
+ * HYDRO_ENOMEM: every member's later calls return that error and nothing
+ * more is issued for the team.  Every member must call leave exactly once
+ * (that frees the team's slot).  hydro_region_create makes n_streams
+ * (1..32) streams and 2 x n_streams arenas of arena_bytes device memory plus
+ * pinned host mirrors; nothing is allocated afterwards.  Destroying a region
+ * with tasks inside is undefined.
+ */
+typedef struct hydro_region hydro_region_t;
+typedef struct {
+  int32_t team;   /* team slot                         */
+  int32_t index;  /* this member's index, 0..size-1    */
+  int32_t size;   /* members of the team               */
+  int32_t stream; /* the team's executor               */
+  uint64_t id;    /* team serial number                */
+} hydro_region_task_t;
+typedef struct {
+  uint64_t tasks, teams, full_teams, uploads, launches, downloads;
+  uint64_t size_hist[11]; /* teams of size 1, 2-3, 4-7, ..., >= 1024 */
+} hydro_region_stats_t;
+int hydro_region_create(hydro_region_t **out, int32_t max_team,
+                        int32_t n_streams, uint64_t arena_bytes);
+int hydro_region_enter(hydro_region_t *r, hydro_region_task_t *task);
+int hydro_region_alloc(hydro_region_t *r, const hydro_region_task_t *task,
+                       uint64_t bytes, int32_t *buffer, void **host_chunk,
+                       void **dev_chunk);
+int hydro_region_buffer(hydro_region_t *r, const hydro_region_task_t *task,
+                        int32_t buffer, void **dev_base, uint64_t *stride);
+int hydro_region_upload(hydro_region_t *r, const hydro_region_task_t *task,
+                        int32_t buffer);
+int hydro_region_download(hydro_region_t *r, const hydro_region_task_t *task,
+                          int32_t buffer);
+int hydro_region_launch(hydro_region_t *r, const hydro_region_task_t *task,
+                        const void *kernel, uint32_t blocks_per_task,
+                        uint32_t threads, uint32_t shmem, void **args);
+int hydro_region_leave(hydro_region_t *r, const hydro_region_task_t *task);
+int hydro_region_stats(hydro_region_t *r, hydro_region_stats_t *out);
+int hydro_region_destroy(hydro_region_t *r);
+
+/*
+ * Kernels of this library that run inside a region (NULL for another
+ * value):
+ *   HYDRO_REGION_STEP8_F6 / _F11: the aggregated 8^3 step, arguments
+ *     (const hydro_subgrid_t *table, int32_t count, double dt, double dx,
+ *      double *amax): member s's descriptor at table[s] (a team buffer of
+ *     32-byte chunks), results as hydro_step, amax of member s at amax[s];
+ *     blocks_per_task 1, threads 192.
+ *   HYDRO_REGION_AXPBY: out = a x + b y over n doubles per member (the
+ *     stage combination of a Runge-Kutta step), arguments
+ *     (const hydro_region_axpby_t *table, int32_t count,
+ *      int32_t blocks_per_task); threads 256.
+ */
+#define HYDRO_REGION_STEP8_F6 0
+#define HYDRO_REGION_STEP8_F11 1
+#define HYDRO_REGION_AXPBY 2
+typedef struct {
+  const double *x;
+  const double *y;
+  double *out;
+  double a;
+  double b;
+  int64_t n;
+} hydro_region_axpby_t;
+const void *hydro_region_kernel(int32_t which);
+
+/*
  * Aggregator: explicit work aggregation of fine-grained sub-grid tasks (the
  * paper's strategy 3, Section V-D).  Tasks submitted while the aggregator's
  * streams are busy are held and launched together as one batch (one kernel

@@ -566,13 +566,13 @@ __global__ void __launch_bounds__(Lds8::kThreads, 2)
 
 // amax slots of a batch set to zero before a multi-block launch (a kernel,
 // so it can live inside a captured graph).
-__global__ void amax_zero_table(const DevDesc* __restrict__ table, int count,
+static __global__ void amax_zero_table(const DevDesc* __restrict__ table, int count,
                                 double* __restrict__ amax_out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) amax_out[table[i].index] = 0.0;
 }
 
-__global__ void amax_zero_args(ArgDescs descs, int count, double* __restrict__ amax_out) {
+static __global__ void amax_zero_args(ArgDescs descs, int count, double* __restrict__ amax_out) {
   const int i = threadIdx.x;
   if (i < count) amax_out[descs.d[i].index] = 0.0;
 }

@@ -73,6 +73,25 @@ class hydro_brick_t(ctypes.Structure):
 BC_PERIODIC = 0
 BC_OUTFLOW = 1
 
+
+class hydro_region_task_t(ctypes.Structure):
+    _fields_ = [("team", ctypes.c_int32), ("index", ctypes.c_int32), ("size", ctypes.c_int32),
+                ("stream", ctypes.c_int32), ("id", ctypes.c_uint64)]
+
+
+class hydro_region_stats_t(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "tasks", "teams", "full_teams", "uploads", "launches", "downloads")] + \
+        [("size_hist", ctypes.c_uint64 * 11)]
+
+
+class hydro_region_axpby_t(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("a", ctypes.c_double), ("b", ctypes.c_double), ("n", ctypes.c_int64)]
+
+
+REGION_STEP8_F6, REGION_STEP8_F11, REGION_AXPBY = 0, 1, 2
+
 _lib = None
 
 
@@ -110,6 +129,29 @@ def lib() -> ctypes.CDLL:
         L.hydro_agg_drain.argtypes = [AP]
         L.hydro_step_streams.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+        RT = ctypes.POINTER(hydro_region_task_t)
+        VP = ctypes.c_void_p
+        L.hydro_region_create.argtypes = [ctypes.POINTER(VP), ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_uint64]
+        L.hydro_region_enter.argtypes = [VP, RT]
+        L.hydro_region_alloc.argtypes = [VP, RT, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(VP), ctypes.POINTER(VP)]
+        L.hydro_region_buffer.argtypes = [VP, RT, ctypes.c_int32, ctypes.POINTER(VP),
+                                          ctypes.POINTER(ctypes.c_uint64)]
+        L.hydro_region_upload.argtypes = [VP, RT, ctypes.c_int32]
+        L.hydro_region_download.argtypes = [VP, RT, ctypes.c_int32]
+        L.hydro_region_launch.argtypes = [VP, RT, VP, ctypes.c_uint32, ctypes.c_uint32,
+                                          ctypes.c_uint32, ctypes.POINTER(VP)]
+        L.hydro_region_leave.argtypes = [VP, RT]
+        L.hydro_region_stats.argtypes = [VP, ctypes.POINTER(hydro_region_stats_t)]
+        L.hydro_region_destroy.argtypes = [VP]
+        for name in ("hydro_region_create", "hydro_region_enter", "hydro_region_alloc",
+                     "hydro_region_buffer", "hydro_region_upload", "hydro_region_download",
+                     "hydro_region_launch", "hydro_region_leave", "hydro_region_stats",
+                     "hydro_region_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+        L.hydro_region_kernel.argtypes = [ctypes.c_int32]
+        L.hydro_region_kernel.restype = VP
         L.hydro_flush.argtypes = [AP]
         L.hydro_progress.argtypes = [AP]
         L.hydro_poll.argtypes = [AP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
@@ -343,6 +385,81 @@ class Plan:
         if self._h:
             _check(lib().hydro_plan_destroy(self._h))
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def region_kernel(which: int) -> int:
+    """Address of a library kernel usable inside a region (REGION_*)."""
+    k = lib().hydro_region_kernel(int(which))
+    if not k:
+        raise HydroError(HYDRO_EINVAL, f"no region kernel {which}")
+    return k
+
+
+class Region:
+    """An aggregation region (hydro_region_*): tasks (host threads) that
+    enter together form a team sharing chunked buffers; uploads, launches and
+    downloads run once for the team, when its last member calls them."""
+
+    def __init__(self, max_team: int, n_streams: int = 1, arena_bytes: int = 1 << 20):
+        h = ctypes.c_void_p()
+        _check(lib().hydro_region_create(ctypes.byref(h), int(max_team), int(n_streams),
+                                         int(arena_bytes)))
+        self._h = h
+
+    def enter(self) -> hydro_region_task_t:
+        t = hydro_region_task_t()
+        _check(lib().hydro_region_enter(self._h, ctypes.byref(t)))
+        return t
+
+    def alloc(self, task, nbytes: int):
+        """(buffer id, host chunk address, device chunk address)."""
+        b = ctypes.c_int32()
+        hp, dp = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib().hydro_region_alloc(self._h, ctypes.byref(task), int(nbytes), ctypes.byref(b),
+                                        ctypes.byref(hp), ctypes.byref(dp)))
+        return b.value, hp.value, dp.value
+
+    def buffer(self, task, b: int):
+        """(device base address, stride) of team buffer b."""
+        base, stride = ctypes.c_void_p(), ctypes.c_uint64()
+        _check(lib().hydro_region_buffer(self._h, ctypes.byref(task), int(b), ctypes.byref(base),
+                                         ctypes.byref(stride)))
+        return base.value, stride.value
+
+    def upload(self, task, b: int) -> None:
+        _check(lib().hydro_region_upload(self._h, ctypes.byref(task), int(b)))
+
+    def download(self, task, b: int) -> None:
+        _check(lib().hydro_region_download(self._h, ctypes.byref(task), int(b)))
+
+    def launch(self, task, kernel: int, blocks_per_task: int, threads: int, args, shmem: int = 0):
+        """args: ctypes values (c_void_p, c_int32, c_double, ...) in the
+        kernel's parameter order."""
+        ptrs = (ctypes.c_void_p * max(len(args), 1))(
+            *[ctypes.cast(ctypes.pointer(a), ctypes.c_void_p) for a in args])
+        _check(lib().hydro_region_launch(self._h, ctypes.byref(task), kernel, int(blocks_per_task),
+                                         int(threads), int(shmem), ptrs))
+
+    def leave(self, task) -> None:
+        _check(lib().hydro_region_leave(self._h, ctypes.byref(task)))
+
+    def stats(self) -> dict:
+        s = hydro_region_stats_t()
+        _check(lib().hydro_region_stats(self._h, ctypes.byref(s)))
+        d = {n: int(getattr(s, n)) for n, _ in s._fields_ if n != "size_hist"}
+        d["size_hist"] = [int(x) for x in s.size_hist]
+        return d
+
+    def close(self) -> None:
+        if self._h:
+            h, self._h = self._h, None
+            _check(lib().hydro_region_destroy(h))
 
     def __del__(self):
         try:

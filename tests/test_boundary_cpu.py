@@ -164,3 +164,20 @@ def test_strategy_and_bulk_calls_check_arguments():
     h = ctypes.c_void_p()
     for k in (0, 129):
         assert L.hydro_agg_create(ctypes.byref(h), 4, 50.0, k, 0, 1) == hydroagg.HYDRO_EINVAL
+
+
+def test_region_calls_check_arguments():
+    L = hydroagg.lib()
+    h = ctypes.c_void_p()
+    for args in ((0, 1, 1 << 20), (4, 0, 1 << 20), (4, 33, 1 << 20), (4, 1, 16)):
+        assert L.hydro_region_create(ctypes.byref(h), *args) == hydroagg.HYDRO_EINVAL, args
+    assert L.hydro_region_create(None, 4, 1, 1 << 20) == hydroagg.HYDRO_EINVAL
+    t = hydroagg.hydro_region_task_t()
+    assert L.hydro_region_enter(None, ctypes.byref(t)) == hydroagg.HYDRO_EINVAL
+    assert L.hydro_region_leave(None, ctypes.byref(t)) == hydroagg.HYDRO_EINVAL
+    assert L.hydro_region_destroy(None) == hydroagg.HYDRO_OK
+    for k in (hydroagg.REGION_STEP8_F6, hydroagg.REGION_STEP8_F11, hydroagg.REGION_AXPBY):
+        assert L.hydro_region_kernel(k)
+    assert not L.hydro_region_kernel(3)
+    assert ctypes.sizeof(hydroagg.hydro_region_task_t) == 24
+    assert ctypes.sizeof(hydroagg.hydro_region_axpby_t) == 48
