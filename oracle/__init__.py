@@ -76,6 +76,12 @@ def _load():
                                     ctypes.c_double, ctypes.c_double, dp, i64p,
                                     ctypes.c_int]
         lib.oracle_step.restype = ctypes.c_int
+        lib.oracle_step26.argtypes = lib.oracle_step.argtypes
+        lib.oracle_step26.restype = ctypes.c_int
+        lib.oracle_point_value.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_int32), dp]
+        lib.oracle_point_value.restype = ctypes.c_int
         lib.oracle_primitive.argtypes = [dp, ctypes.c_int, dp]
         lib.oracle_primitive.restype = None
         lib.oracle_ppm_line.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, dp, i64p]
@@ -100,8 +106,31 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+def step26(u_in: np.ndarray, dt: float, dx: float, levels=None, u_out=None,
+           counters: bool = False, nthreads: int = 1):
+    """Q1-Q7: the 26-point form (values at the 26 points of each cell's
+    surface, central-upwind fluxes at the 9 points of every face, Simpson's
+    rule over each face), with the arguments and results of step().  The
+    sub-grids' edge and corner ghosts are read."""
+    return step(u_in, dt, dx, levels=levels, u_out=u_out, counters=counters,
+                nthreads=nthreads, _points=26)
+
+
+def point_value(q_block, x: int, y: int, z: int, e):
+    """Q2+Q3: the value of stored cell (x, y, z) of a block of primitives
+    q_block[M, M, M, F] toward direction e (three of -1, 0, 1)."""
+    lib = _load()
+    q = _f64(q_block)
+    M, nf = q.shape[0], q.shape[3]
+    ev = (ctypes.c_int32 * 3)(*[int(v) for v in e])
+    out = np.empty(nf, dtype=np.float64)
+    if lib.oracle_point_value(_dp(q), M, nf, int(x), int(y), int(z), ev, _dp(out)) != 0:
+        raise ValueError("stencil outside the block or bad direction")
+    return out
+
+
 def step(u_in: np.ndarray, dt: float, dx: float, levels=None, u_out=None,
-         counters: bool = False, nthreads: int = 1):
+         counters: bool = False, nthreads: int = 1, _points: int = 6):
     """O1-O7 on a batch of sub-grids.
 
     ``u_in``: float64 array [count, F, M, M, M] (M = N + 6), SoA, x fastest.
@@ -137,11 +166,12 @@ def step(u_in: np.ndarray, dt: float, dx: float, levels=None, u_out=None,
         descs[s].reserved = 0
     amax = np.zeros(max(count, 1), dtype=np.float64)
     cnt = np.zeros(len(COUNTER_NAMES), dtype=np.int64)
-    rc = lib.oracle_step(descs, count, float(dt), float(dx), _dp(amax),
-                         cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if counters else None,
-                         int(nthreads))
+    fn = lib.oracle_step26 if _points == 26 else lib.oracle_step
+    rc = fn(descs, count, float(dt), float(dx), _dp(amax),
+            cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if counters else None,
+            int(nthreads))
     if rc != 0:
-        raise ValueError("oracle_step rejected its arguments")
+        raise ValueError("oracle step rejected its arguments")
     amax = amax[:count]
     if counters:
         return u_out, amax, dict(zip(COUNTER_NAMES, (int(c) for c in cnt)))

@@ -21,7 +21,9 @@
  *   O3  the Colella-Woodward monotonicity constraint on each cell's parabola.
  *   O4  face states: W- = right edge of the left cell, W+ = left edge of the
  *       right cell, at the centre of every face (the 6 face-centre points of
- *       the 26 quadrature points; edge and vertex points are not evaluated).
+ *       the 26 quadrature points; the full 26-point form, with edge and
+ *       vertex points and Newton-Cotes quadrature over each face, is the
+ *       separate oracle_step26 below: Q1-Q7).
  *   O5  physical state U(W) and flux F_d(W) of the ideal-gas Euler system.
  *   O6  central-upwind (Kurganov-Noelle-Petrova) numerical flux with
  *       one-sided speeds a+ and a-; amax = max over faces of max(a+, -a-)
@@ -295,6 +297,126 @@ static double step_one(const oracle_subgrid *sg, double dt, double dx,
   return amax;
 }
 
+/* ---- the 26-point form (Section IV-B: reconstruction at the 26 points on
+ * a cell's surface -- 6 face centres, 12 edge midpoints, 8 vertices --
+ * central-upwind fluxes at those points, Newton-Cotes quadrature over each
+ * face) ---------------------------------------------------------------------
+ *   Q1  primitives of every stored cell (edge and corner ghosts included).
+ *   Q2+Q3  the value of cell c at the point c + e/2 of its surface, for each
+ *       of the 26 directions e in {-1,0,1}^3 \ {0}: PPM (O2 + O3) along the
+ *       line of cells c + k e, k = -2..2, oriented along e; the value is the
+ *       right edge (toward +e) of c's limited parabola on that line.
+ *   Q4  a face normal to axis d between cells c and c + n (n the unit vector
+ *       of d) has 9 points, offsets (s1, s2) in {-1,0,1}^2 along its two
+ *       transverse axes t1 < t2: W- = value of c toward n + s1 t1 + s2 t2,
+ *       W+ = value of c + n toward -n + s1 t1 + s2 t2.
+ *   Q5+Q6  central-upwind flux along d at each point (O5, O6); the face flux
+ *       is Simpson's rule in both transverse directions,
+ *       (16 F_centre + 4 sum F_edge-midpoints + sum F_vertices) / 36, summed
+ *       in the order s2 = -1..1 (outer), s1 = -1..1 (inner); amax covers
+ *       every point of every face.
+ *   Q7  as O7.
+ * The same faces as the face-centre form (N+1 per line, transverse
+ * coordinates interior); their stencils reach 2 cells along e from cells
+ * 2..M-3 of the normal axis, inside the 3 ghost layers. */
+
+/* value of the stored cell (x, y, z) toward direction e (Q2+Q3) */
+static void point_value(const double *q, int M, int nf, int x, int y, int z,
+                        const int e[3], double *out, int64_t *cnt) {
+  double line[5 * 16], qL[5 * 16], qR[5 * 16];
+  for (int k = -2; k <= 2; ++k) {
+    size_t c = ((size_t)(z + k * e[2]) * M + (y + k * e[1])) * M + (x + k * e[0]);
+    memcpy(&line[(k + 2) * nf], &q[c * nf], sizeof(double) * nf);
+  }
+  ppm_line(line, 5, nf, qL, qR, cnt);
+  memcpy(out, &qR[2 * nf], sizeof(double) * nf);
+}
+
+static double step26_one(const oracle_subgrid *sg, double dt, double dx,
+                         int64_t *cnt) {
+  const int N = sg->n, nf = sg->nfields, M = N + 2 * GHOST;
+  const double dxs = ldexp(dx, -sg->level);
+  const double lambda = dt / dxs;
+  const size_t ncell = (size_t)M * M * M;
+  double amax = 0.0;
+
+  /* Q1 */
+  double *q = (double *)malloc(sizeof(double) * ncell * nf);
+  for (int z = 0; z < M; ++z)
+    for (int y = 0; y < M; ++y)
+      for (int x = 0; x < M; ++x) {
+        double U[16];
+        size_t c = ((size_t)z * M + y) * M + x;
+        for (int f = 0; f < nf; ++f) U[f] = sg->u_in[at(M, f, z, y, x)];
+        to_primitive(U, nf, &q[c * nf]);
+      }
+
+  const size_t nint = (size_t)N * N * N;
+  double *dF = (double *)calloc(3 * nint * nf, sizeof(double));
+  double *Fh = (double *)malloc(sizeof(double) * M * nf);
+  for (int d = 0; d < 3; ++d) {
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    for (int b = 0; b < N; ++b)
+      for (int a = 0; a < N; ++a) {
+        /* faces i+1/2 of the line along d through transverse (a, b) */
+        for (int i = 2; i <= M - 4; ++i) {
+          int lo[3], hi[3];
+          lo[d] = i;
+          lo[t1] = GHOST + a;
+          lo[t2] = GHOST + b;
+          memcpy(hi, lo, sizeof lo);
+          hi[d] = i + 1;
+          double acc[16] = {0};
+          for (int s2 = -1; s2 <= 1; ++s2)
+            for (int s1 = -1; s1 <= 1; ++s1) {
+              int em[3] = {0, 0, 0}, ep[3] = {0, 0, 0};
+              em[d] = 1;
+              ep[d] = -1;
+              em[t1] = ep[t1] = s1;
+              em[t2] = ep[t2] = s2;
+              double Wm[16], Wp[16], F[16];
+              point_value(q, M, nf, lo[0], lo[1], lo[2], em, Wm, cnt);
+              point_value(q, M, nf, hi[0], hi[1], hi[2], ep, Wp, cnt);
+              if (cnt && (Wm[0] <= 0.0 || Wm[4] <= 0.0 || Wp[0] <= 0.0 || Wp[4] <= 0.0))
+                cnt[CNT_NONPOS_FACE]++;
+              double sp = knp_flux(Wm, Wp, nf, d, F);
+              if (sp > amax) amax = sp;
+              const double w = (s1 == 0 && s2 == 0) ? 16.0 : (s1 == 0 || s2 == 0) ? 4.0 : 1.0;
+              for (int f = 0; f < nf; ++f) acc[f] = acc[f] + w * F[f];
+            }
+          for (int f = 0; f < nf; ++f) Fh[i * nf + f] = acc[f] / 36.0;
+        }
+        for (int i = GHOST; i < GHOST + N; ++i) {
+          int ix, iy, iz;
+          if (d == 0) { ix = i - GHOST; iy = a; iz = b; }
+          else if (d == 1) { ix = a; iy = i - GHOST; iz = b; }
+          else { ix = a; iy = b; iz = i - GHOST; }
+          size_t c = ((size_t)iz * N + iy) * N + ix;
+          for (int f = 0; f < nf; ++f)
+            dF[((size_t)d * nint + c) * nf + f] = Fh[i * nf + f] - Fh[(i - 1) * nf + f];
+        }
+      }
+  }
+
+  /* Q7 */
+  for (int z = 0; z < N; ++z)
+    for (int y = 0; y < N; ++y)
+      for (int x = 0; x < N; ++x) {
+        size_t c = ((size_t)z * N + y) * N + x;
+        for (int f = 0; f < nf; ++f) {
+          double s = dF[(0 * nint + c) * nf + f];
+          s = s + dF[(1 * nint + c) * nf + f];
+          s = s + dF[(2 * nint + c) * nf + f];
+          size_t g = at(M, f, z + GHOST, y + GHOST, x + GHOST);
+          sg->u_out[g] = sg->u_in[g] - lambda * s;
+        }
+      }
+  free(q);
+  free(dF);
+  free(Fh);
+  return amax;
+}
+
 /* ---- exported entry points ------------------------------------------- */
 
 int oracle_ncounters(void) { return ORACLE_NCOUNT; }
@@ -333,6 +455,48 @@ int oracle_step(const oracle_subgrid *sg, int count, double dt, double dx,
 #else
   return -1;
 #endif
+}
+
+/* One stage of the 26-point form over `count` independent sub-grids, with
+ * the arguments and results of oracle_step.  Sub-grids need their edge and
+ * corner ghosts filled (the face-centre form never reads them). */
+int oracle_step26(const oracle_subgrid *sg, int count, double dt, double dx,
+                  double *amax, int64_t *counters, int nthreads) {
+  if (count < 0 || (count > 0 && !sg) || !(dx > 0.0) || !(dt >= 0.0)) return -1;
+  for (int s = 0; s < count; ++s)
+    if (bad_subgrid(&sg[s]) || sg[s].n < 1) return -1;
+  if (nthreads <= 1) {
+    for (int s = 0; s < count; ++s) {
+      double a = step26_one(&sg[s], dt, dx, counters);
+      if (amax) amax[s] = a;
+    }
+    return 0;
+  }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+  for (int s = 0; s < count; ++s) {
+    double a = step26_one(&sg[s], dt, dx, NULL);
+    if (amax) amax[s] = a;
+  }
+  return 0;
+#else
+  return -1;
+#endif
+}
+
+/* Q2+Q3 at one cell of a stored block of primitives q[M^3][nf]: the value of
+ * cell (x, y, z) toward direction e (for tests of the point geometry). */
+int oracle_point_value(const double *q, int M, int nf, int x, int y, int z,
+                       const int32_t *e, double *out) {
+  int ee[3] = {e[0], e[1], e[2]};
+  for (int k = 0; k < 3; ++k) {
+    if (ee[k] < -1 || ee[k] > 1) return -1;
+    int c = k == 0 ? x : k == 1 ? y : z;
+    if (c - 2 * abs(ee[k]) < 0 || c + 2 * abs(ee[k]) >= M) return -1;
+  }
+  if (!ee[0] && !ee[1] && !ee[2]) return -1;
+  point_value(q, M, nf, x, y, z, ee, out, NULL);
+  return 0;
 }
 
 /* Building blocks exposed so tests can pin them in isolation. */
