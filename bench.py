@@ -291,6 +291,32 @@ def strategies_leg(args, torch, hydroagg, workloads, dev, stream):
                              "iteration, transfers, CPU work), the hydro kernel alone here"}
 
 
+def step26_leg(args, torch, hydroagg, u_in, u_out, dt, dx, count, n, nf, stream):
+    """The 26-point form (Section IV-B: 9 central-upwind flux points per face,
+    Simpson's rule) on the headline batch and outputs; per-launch events."""
+    descs = hydroagg.subgrids(u_in, u_out)
+    for _ in range(2):
+        hydroagg.hydro_step26(descs, dt, dx, None, stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.step26_reps)]
+    for a_, b_ in ev:
+        a_.record(stream)
+        hydroagg.hydro_step26(descs, dt, dx, None, stream)
+        b_.record(stream)
+    torch.cuda.synchronize()
+    ms = statistics.median(a_.elapsed_time(b_) for a_, b_ in ev)
+    cells = count * n ** 3
+    log(f"26-point step: {ms * 1e3:.1f} us per step ({cells / (ms * 1e-3) / 1e9:.3f} G cell-updates/s)")
+    return {"workload": f"{count} sub-grids of {n}^3, {nf} FP64 fields, random smooth state, "
+                        "updated interiors written [F][n][n][n]",
+            "what": "26 reconstruction points per cell, 9 central-upwind flux points per face, "
+                    "Simpson's rule over each face; one launch (descriptor copy included)",
+            "ms_per_step": round(ms, 4), "value": round(cells / (ms * 1e-3), 1),
+            "unit": "cell-updates/s", "flux_points_per_step": count * 3 * 9 * (n + 1) * n * n,
+            "reps": args.step26_reps}
+
+
 def _time_oracle(oracle, U, dt, dx, threads, seconds, levels=None, reps=2):
     """Median wall time of oracle.step over repetitions lasting >= seconds."""
     times = []
@@ -531,6 +557,8 @@ def main():
     ap.add_argument("--learned-splits", type=int, default=10)
     ap.add_argument("--no-timestep", action="store_true", help="skip the SSP-RK3 time-step leg")
     ap.add_argument("--no-strategies", action="store_true", help="skip the strategy comparison leg")
+    ap.add_argument("--step26-reps", type=int, default=10,
+                    help="timed launches of the 26-point step (0: skip)")
     ap.add_argument("--strategy-reps", type=int, default=3)
     ap.add_argument("--strategy-streams", type=int, nargs="*",
                     default=[1, 2, 4, 8, 16, 32, 64, 128])
@@ -693,6 +721,10 @@ def main():
         copy_gbs = 2 * u_in.numel() * 8 / (copy_ms * 1e-3) / 1e9
         log(f"device copy of {u_in.numel() * 8 / 1e9:.2f} GB: {copy_ms * 1e3:.1f} us, {copy_gbs:.0f} GB/s")
 
+    step26 = None
+    if args.step26_reps > 0 and n == 8:
+        step26 = step26_leg(args, torch, hydroagg, u_in, u_out, dt, dx, count, n, nf, stream)
+
     floor_b, tile_b = bytes_per_subgrid(n, nf)
     achieved = tile_b * count / (kernel_ms * 1e-3) / 1e9
     achieved_floor = floor_b * count / (kernel_ms * 1e-3) / 1e9
@@ -786,6 +818,7 @@ def main():
         "learned_width": learned_res,
         "timestep": timestep,
         "strategies": strategies,
+        "step26": step26,
         "tile_autotune": tiles,
     }
     plan.close()

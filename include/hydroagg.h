@@ -150,6 +150,23 @@ int hydro_step_streams(const hydro_subgrid_t *sg, int32_t count, double dt,
                        void *stream);
 
 /*
+ * hydro_step26 -- the 26-point form of the aggregated step (Section IV-B):
+ * the evolved variables are reconstructed (piecewise-parabolic, with the
+ * monotonicity constraint) at the 26 points of each cell's surface -- face
+ * centres, edge midpoints and vertices, each along the line of cells toward
+ * that point -- central-upwind fluxes are evaluated at the 9 points of
+ * every face, and Simpson's rule in both transverse directions integrates
+ * them over the face (weights 16, 4, 1 over 36 for centre, edge midpoints,
+ * vertices).  hydro_step evaluates the face centres only.  Sub-grids of
+ * n = 8, all of one field count (HYDRO_EINVAL otherwise); their edge and
+ * corner ghosts are read.  Arguments, layouts, amax (over all 9 points of
+ * every face) and other errors as hydro_step.  One launch per call (of at
+ * most 65536 sub-grids), one 576-lane work-group per sub-grid.
+ */
+int hydro_step26(const hydro_subgrid_t *sg, int32_t count, double dt,
+                 double dx, double *amax_dev, void *stream);
+
+/*
  * hydro_step_each -- the non-aggregated baseline: the same kernel launched
  * once per sub-grid (the paper's "1 executor, max aggregated 1" setting,
  * Section VI-B), every launch on `stream`, each carrying its one descriptor

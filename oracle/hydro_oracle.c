@@ -205,12 +205,51 @@ static double knp_flux(const double *Wm, const double *Wp, int nf, int d,
   return fmax(ap, -am);
 }
 
+/* ---- steps shared by both forms ----------------------------------------- */
+
+/* lambda_s = dt / dx_s with dx_s = dx 2^-level */
+static double lambda_of(const oracle_subgrid *sg, double dt, double dx) {
+  return dt / ldexp(dx, -sg->level);
+}
+
+/* F_{+} - F_{-} of direction d for the interior cells of the line through
+ * transverse (a, b): Fh[i] is the flux through face i+1/2 (stored i). */
+static void line_differences(double *dF, int d, int a, int b, const double *Fh, int N, int nf) {
+  const size_t nint = (size_t)N * N * N;
+  for (int i = GHOST; i < GHOST + N; ++i) {
+    int ix, iy, iz;
+    if (d == 0) { ix = i - GHOST; iy = a; iz = b; }
+    else if (d == 1) { ix = a; iy = i - GHOST; iz = b; }
+    else { ix = a; iy = b; iz = i - GHOST; }
+    size_t c = ((size_t)iz * N + iy) * N + ix;
+    for (int f = 0; f < nf; ++f)
+      dF[((size_t)d * nint + c) * nf + f] = Fh[i * nf + f] - Fh[(i - 1) * nf + f];
+  }
+}
+
+/* O7 / Q7: x, then y, then z; then scale by dt/dx_s. */
+static void apply_update(const oracle_subgrid *sg, const double *dF, double lambda) {
+  const int N = sg->n, nf = sg->nfields, M = N + 2 * GHOST;
+  const size_t nint = (size_t)N * N * N;
+  for (int z = 0; z < N; ++z)
+    for (int y = 0; y < N; ++y)
+      for (int x = 0; x < N; ++x) {
+        size_t c = ((size_t)z * N + y) * N + x;
+        for (int f = 0; f < nf; ++f) {
+          double s = dF[(0 * nint + c) * nf + f];
+          s = s + dF[(1 * nint + c) * nf + f];
+          s = s + dF[(2 * nint + c) * nf + f];
+          size_t g = at(M, f, z + GHOST, y + GHOST, x + GHOST);
+          sg->u_out[g] = sg->u_in[g] - lambda * s;
+        }
+      }
+}
+
 /* ---- O1..O7 for one sub-grid ------------------------------------------- */
 static double step_one(const oracle_subgrid *sg, double dt, double dx,
                        int64_t *cnt) {
   const int N = sg->n, nf = sg->nfields, M = N + 2 * GHOST;
-  const double dxs = ldexp(dx, -sg->level);
-  const double lambda = dt / dxs;
+  const double lambda = lambda_of(sg, dt, dx);
   const size_t ncell = (size_t)M * M * M;
   double amax = 0.0;
 
@@ -262,31 +301,12 @@ static double step_one(const oracle_subgrid *sg, double dt, double dx,
           if (s > amax) amax = s;
         }
         /* F_{+} - F_{-} for interior stored cells i = 3..M-4. */
-        for (int i = GHOST; i < GHOST + N; ++i) {
-          int ix, iy, iz;
-          if (d == 0) { ix = i - GHOST; iy = a; iz = b; }
-          else if (d == 1) { ix = a; iy = i - GHOST; iz = b; }
-          else { ix = a; iy = b; iz = i - GHOST; }
-          size_t c = ((size_t)iz * N + iy) * N + ix;
-          for (int f = 0; f < nf; ++f)
-            dF[((size_t)d * nint + c) * nf + f] = Fh[i * nf + f] - Fh[(i - 1) * nf + f];
-        }
+        line_differences(dF, d, a, b, Fh, N, nf);
       }
   }
 
-  /* O7: x, then y, then z; then scale by dt/dx_s. */
-  for (int z = 0; z < N; ++z)
-    for (int y = 0; y < N; ++y)
-      for (int x = 0; x < N; ++x) {
-        size_t c = ((size_t)z * N + y) * N + x;
-        for (int f = 0; f < nf; ++f) {
-          double s = dF[(0 * nint + c) * nf + f];
-          s = s + dF[(1 * nint + c) * nf + f];
-          s = s + dF[(2 * nint + c) * nf + f];
-          size_t g = at(M, f, z + GHOST, y + GHOST, x + GHOST);
-          sg->u_out[g] = sg->u_in[g] - lambda * s;
-        }
-      }
+  /* O7 */
+  apply_update(sg, dF, lambda);
 
   free(q);
   free(dF);
@@ -335,8 +355,7 @@ static void point_value(const double *q, int M, int nf, int x, int y, int z,
 static double step26_one(const oracle_subgrid *sg, double dt, double dx,
                          int64_t *cnt) {
   const int N = sg->n, nf = sg->nfields, M = N + 2 * GHOST;
-  const double dxs = ldexp(dx, -sg->level);
-  const double lambda = dt / dxs;
+  const double lambda = lambda_of(sg, dt, dx);
   const size_t ncell = (size_t)M * M * M;
   double amax = 0.0;
 
@@ -358,8 +377,9 @@ static double step26_one(const oracle_subgrid *sg, double dt, double dx,
     const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     for (int b = 0; b < N; ++b)
       for (int a = 0; a < N; ++a) {
-        /* faces i+1/2 of the line along d through transverse (a, b) */
-        for (int i = 2; i <= M - 4; ++i) {
+        /* faces i+1/2 of the line along d through transverse (a, b): the
+         * faces of its interior cells GHOST..GHOST+N-1 */
+        for (int i = GHOST - 1; i <= GHOST + N - 1; ++i) {
           int lo[3], hi[3];
           lo[d] = i;
           lo[t1] = GHOST + a;
@@ -386,31 +406,12 @@ static double step26_one(const oracle_subgrid *sg, double dt, double dx,
             }
           for (int f = 0; f < nf; ++f) Fh[i * nf + f] = acc[f] / 36.0;
         }
-        for (int i = GHOST; i < GHOST + N; ++i) {
-          int ix, iy, iz;
-          if (d == 0) { ix = i - GHOST; iy = a; iz = b; }
-          else if (d == 1) { ix = a; iy = i - GHOST; iz = b; }
-          else { ix = a; iy = b; iz = i - GHOST; }
-          size_t c = ((size_t)iz * N + iy) * N + ix;
-          for (int f = 0; f < nf; ++f)
-            dF[((size_t)d * nint + c) * nf + f] = Fh[i * nf + f] - Fh[(i - 1) * nf + f];
-        }
+        line_differences(dF, d, a, b, Fh, N, nf);
       }
   }
 
-  /* Q7 */
-  for (int z = 0; z < N; ++z)
-    for (int y = 0; y < N; ++y)
-      for (int x = 0; x < N; ++x) {
-        size_t c = ((size_t)z * N + y) * N + x;
-        for (int f = 0; f < nf; ++f) {
-          double s = dF[(0 * nint + c) * nf + f];
-          s = s + dF[(1 * nint + c) * nf + f];
-          s = s + dF[(2 * nint + c) * nf + f];
-          size_t g = at(M, f, z + GHOST, y + GHOST, x + GHOST);
-          sg->u_out[g] = sg->u_in[g] - lambda * s;
-        }
-      }
+  /* Q7 (= O7) */
+  apply_update(sg, dF, lambda);
   free(q);
   free(dF);
   free(Fh);

@@ -40,7 +40,7 @@ def source_hash() -> str:
 
 KERNEL_SOURCES = [os.path.join(HERE, "csrc", f)
                   for f in ("hydro_kernel.hpp", "hydro_lds8.hpp", "hydro_q4.hpp",
-                            "hydro_mixed.hpp", "hydro_pattern.hpp")]
+                            "hydro_mixed.hpp", "hydro_pattern.hpp", "hydro_step26.hpp")]
 
 
 def kernel_hash() -> str:

@@ -25,6 +25,7 @@
 #include "hydro_q4.hpp"
 #include "hydro_mixed.hpp"
 #include "hydro_pattern.hpp"
+#include "hydro_step26.hpp"
 #include "internal.hpp"
 
 using hydro::ArgDescs;
@@ -741,6 +742,40 @@ int hydro_step_streams(const hydro_subgrid_t* sg, int32_t count, double dt, doub
   for (int j = 0; j < k; ++j) {
     HIP_TRY(hipEventRecord(p.done[j], p.s[j]));
     HIP_TRY(hipStreamWaitEvent(caller, p.done[j], 0));
+  }
+  return HYDRO_OK;
+}
+
+int hydro_step26(const hydro_subgrid_t* sg, int32_t count, double dt, double dx,
+                 double* amax_dev, void* stream) {
+  g_err[0] = '\0';
+  int rc = validate(sg, count, dt, dx);
+  if (rc) return rc;
+  if (count == 0) return HYDRO_OK;
+  const int nf = sg[0].nfields;
+  for (int i = 0; i < count; ++i)
+    if (sg[i].n != 8 || sg[i].nfields != nf)
+      return fail(HYDRO_EINVAL, "sub-grid %d: the 26-point step takes n = 8 and one field count", i);
+  DeviceState* st;
+  rc = device_state(&st);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  for (int base = 0; base < count; base += kSlotCap) {
+    const int n = count - base < kSlotCap ? count - base : kSlotCap;
+    TableLease t;
+    rc = lease_table(st, nullptr, t);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) t.host[i] = to_dev(sg[base + i], base + i);
+    HIP_TRY(hipMemcpyAsync(t.dev, t.host, sizeof(DevDesc) * n, hipMemcpyHostToDevice, s));
+    if (nf == 11)
+      hipLaunchKernelGGL(hydro::hydro_step26_kernel<11>, dim3(n), dim3(hydro::S26::kThreads), 0, s,
+                         t.dev, n, dt, dx, amax_dev);
+    else
+      hipLaunchKernelGGL(hydro::hydro_step26_kernel<6>, dim3(n), dim3(hydro::S26::kThreads), 0, s,
+                         t.dev, n, dt, dx, amax_dev);
+    HIP_TRY(hipGetLastError());
+    rc = release_table(t, s);
+    if (rc) return rc;
   }
   return HYDRO_OK;
 }

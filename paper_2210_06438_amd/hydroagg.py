@@ -104,7 +104,7 @@ def lib() -> ctypes.CDLL:
                                "`python -m paper_2210_06438_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.POINTER(hydro_subgrid_t)
-        for name in ("hydro_step", "hydro_step_each", "hydro_step_static"):
+        for name in ("hydro_step", "hydro_step_each", "hydro_step_static", "hydro_step26"):
             f = getattr(L, name)
             f.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                           ctypes.c_void_p, ctypes.c_void_p]
@@ -282,6 +282,12 @@ def hydro_step_static(descs, dt: float, dx: float, amax=None, stream=None) -> No
     nothing; at most STATIC_MAX sub-grids; overlapping calls on one GPU race)."""
     arr, count = descs
     _check(lib().hydro_step_static(arr, count, float(dt), float(dx), _ptr(amax), _stream(stream)))
+
+
+def hydro_step26(descs, dt: float, dx: float, amax=None, stream=None) -> None:
+    """The 26-point form (9 flux points per face, Simpson's rule), n = 8."""
+    arr, count = descs
+    _check(lib().hydro_step26(arr, count, float(dt), float(dx), _ptr(amax), _stream(stream)))
 
 
 def hydro_step_streams(descs, dt: float, dx: float, amax=None, n_streams: int = 1,

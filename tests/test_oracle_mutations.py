@@ -30,12 +30,33 @@ MUTATIONS = [
     ("wrong internal energy factor", "U[4] = W[4] / (GAMMA - 1.0) +", "U[4] = W[4] / (GAMMA) +"),
 ]
 
+# mistakes in the 26-point form, caught by its own pins
+MUTATIONS26 = [
+    ("Simpson weights of edge midpoints and vertices swapped",
+     "(s1 == 0 || s2 == 0) ? 4.0 : 1.0", "(s1 == 0 || s2 == 0) ? 1.0 : 4.0"),
+    ("face quadrature not normalised", "Fh[i * nf + f] = acc[f] / 36.0;", "Fh[i * nf + f] = acc[f] / 32.0;"),
+    ("high cell's point direction flipped", "ep[d] = -1;", "ep[d] = 1;"),
+    ("high cell's transverse offset mirrored", "em[t1] = ep[t1] = s1;", "em[t1] = s1;\n              ep[t1] = -s1;"),
+    ("value taken toward -e", "memcpy(out, &qR[2 * nf], sizeof(double) * nf);",
+     "memcpy(out, &qL[2 * nf], sizeof(double) * nf);"),
+]
+
 PINS = ["tests/test_oracle_pins.py"]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("desc,old,new", MUTATIONS26, ids=[m[0] for m in MUTATIONS26])
+def test_planted_mistake_in_the_26_point_form_is_caught(tmp_path, desc, old, new):
+    _planted(tmp_path, desc, old, new, ["tests/test_oracle26.py"])
 
 
 @pytest.mark.slow
 @pytest.mark.parametrize("desc,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
 def test_planted_mistake_is_caught(tmp_path, desc, old, new):
+    _planted(tmp_path, desc, old, new, PINS)
+
+
+def _planted(tmp_path, desc, old, new, pins):
     for d in ("oracle", "tests", "paper_2210_06438_amd"):
         shutil.copytree(os.path.join(ROOT, d), tmp_path / d,
                         ignore=shutil.ignore_patterns("*.so", "__pycache__"))
@@ -45,7 +66,7 @@ def test_planted_mistake_is_caught(tmp_path, desc, old, new):
     assert text.count(old) == 1, f"mutation site not unique: {old!r}"
     src.write_text(text.replace(old, new))
     env = dict(os.environ, PYTHONDONTWRITEBYTECODE="1")
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", *PINS],
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", *pins],
                        cwd=tmp_path, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"pins did not catch: {desc}\n{r.stdout[-2000:]}"
     assert "failed" in r.stdout, r.stdout[-2000:]
