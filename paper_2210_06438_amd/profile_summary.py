@@ -148,6 +148,8 @@ def main_step(argv):
     print("\n".join(lines))
 
 
+CUS = 256   # compute units of an MI355X
+
 PASS1 = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64",
          "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_LDS", "SQ_INSTS_SALU"]
 PASS2 = ["SQ_WAVES", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_ACTIVE_INST_VALU",
@@ -216,7 +218,10 @@ def main_sq(argv):
         f"| wave life (SQ_WAVE_CYCLES, read as 4-cycle units) | {wave_q / waves * 4 / 2.4e3:.1f} us at 2.4 GHz |",
         f"| VALU busy per wave (SQ_ACTIVE_INST_VALU) | {valu_q / waves * 4 / 2.4e3:.1f} us "
         f"({valu_q / wave_q:.0%} of its life) |",
-        f"| LDS active / bank-conflict cycles per wave | {lds_q / waves * 4:.0f} / {conf_q / waves * 4:.0f} |",
+        f"| LDS active per wave (SQ_ACTIVE_INST_LDS, 4-cycle units) | {lds_q / waves * 4:.0f} cycles |",
+        f"| LDS bank-conflict stall (SQ_LDS_BANK_CONFLICT, counted per CU, summed over the "
+        f"{CUS} CUs) | {conf_q:.3g} cycles per launch = {conf_q / CUS / 2.4e3:.1f} us per CU at "
+        f"2.4 GHz ({conf_q / CUS / 2.4e3 / (ks['avg_ns'] / 1e3):.0%} of the launch) |",
         "",
     ]
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
