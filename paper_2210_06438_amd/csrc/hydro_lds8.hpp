@@ -440,10 +440,18 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int
   // group.  The second burst goes to LDS (tin regions NA..) during the first
   // group, which reads only regions 0..NA-1.
   static_assert(NA <= 3 && NB <= 3, "passive groups of at most 3 fields");
+  // Every lane stores fma(pa, dF, pz u) with the cell's staged value u: the
+  // x and y lanes their difference dF (pa = 1, pz = 0: dF + 0 is dF), the z
+  // lanes u - lambda dF (pa = -lambda, pz = 1), one rounding as before.
+  const double pa = dir == 2 ? -lambda : 1.0;
+  const double pz = dir == 2 ? 1.0 : 0.0;
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     const int r = p < NA ? p : p - NA;
     double* const zr = r < 2 ? acc + (3 + r) * P : held + 3 * P;
+    // the wave's destination region for this field (uniform): no branch in
+    // the march, so the scheduler can overlap the positions and fields
+    double* const dst = dir == 0 ? acc + r * P : dir == 1 ? held + r * P : zr;
     Recon<1> rc;
     double Fprev = 0.0;
     double q[1], Wm[1], Wp[1];
@@ -468,12 +476,7 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int
         const double Fh = wm[i - 5] * Wm[0] + wp[i - 5] * Wp[0];
         if (i >= 6) {
           const int cell = lbase + (i - 6) * lstride;
-          if (dir == 0)
-            acc[r * P + cell] = Fh - Fprev;
-          else if (dir == 1)
-            held[r * P + cell] = Fh - Fprev;
-          else
-            zr[cell] = tin[p * P + cell] - lambda * (Fh - Fprev);
+          dst[cell] = fma(pa, Fh - Fprev, pz * tin[p * P + cell]);
         }
         Fprev = Fh;
       }

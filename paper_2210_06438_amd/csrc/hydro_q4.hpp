@@ -216,6 +216,12 @@ __device__ __forceinline__ void q4_step(const DevDesc& d, int group, double dt, 
       __builtin_amdgcn_sched_barrier(0);
     }
   }
+  // The largest signal speed is reduced across the wave now and parked in
+  // LDS: reduced at the end, the compiler keeps both speeds of every face
+  // live through the whole passive phase.  The barriers of that phase order
+  // these stores before the final read.
+  smax = wave_max(smax);
+  if (l == 0) red[dir] = smax;
 
   // ---- all passive fields in one burst ----------------------------------
   Share4<NP> ps;
@@ -286,9 +292,6 @@ __device__ __forceinline__ void q4_step(const DevDesc& d, int group, double dt, 
   }
 
   if (amax_out) {
-    smax = wave_max(smax);
-    if (l == 0) red[dir] = smax;
-    __syncthreads();
     if (t == 0) {
       const double m = fmax(fmax(red[0], red[1]), red[2]);
       if constexpr (PARTS)
