@@ -524,17 +524,18 @@ int hydro_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t
 
 /*
  * hydro_math_check -- diagnostic: evaluates, on the device, the reciprocal
- * and square-root routines every hydro kernel uses (1/rho in the primitive
- * recovery, the sound speed sqrt(gamma p / rho) and the 1/(a+ - a-) of the
- * central-upwind flux, Section IV-B) on n caller-given arguments, so that
- * tests can bound their error against correctly rounded IEEE results.
+ * and reciprocal-square-root routines every hydro kernel uses (1/rho in the
+ * primitive recovery, the sound speed sqrt(gamma p / rho) =
+ * gamma p / sqrt(gamma p rho) and the 1/(a+ - a-) of the central-upwind
+ * flux, Section IV-B) on n caller-given arguments, so that tests can bound
+ * their error against correctly rounded results.
  *   x          device, n doubles, each positive and normal.
- *   recip_out  device, n doubles: recip(x[i]).
- *   sqrt_out   device, n doubles: sqrt(x[i]).
+ *   recip_out  device, n doubles: recip(x[i]) ~ 1/x[i].
+ *   rsqrt_out  device, n doubles: rsq(x[i]) ~ 1/sqrt(x[i]).
  * Errors: HYDRO_EINVAL for n < 0 or a NULL pointer with n > 0; HYDRO_EHIP if
  * the launch fails.  Enqueues on `stream` (NULL = default stream).
  */
-int hydro_math_check(const double *x, int32_t n, double *recip_out, double *sqrt_out,
+int hydro_math_check(const double *x, int32_t n, double *recip_out, double *rsqrt_out,
                      void *stream);
 
 /* Thread-local text of the last error on the calling thread ("" if none). */

@@ -963,28 +963,28 @@ int hydro_get_tile(int32_t n, int32_t nfields, int32_t* tile) {
 }  // extern "C"
 
 namespace hydro {
-// The kernels' reciprocal and square root on caller-given arguments
-// (diagnostic entry point hydro_math_check).
+// The kernels' reciprocal and reciprocal square root on caller-given
+// arguments (diagnostic entry point hydro_math_check).
 __global__ void math_check_kernel(const double* __restrict__ x, int n,
                                   double* __restrict__ r, double* __restrict__ q) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     r[i] = recip(x[i]);
-    q[i] = sqrt_pos(x[i]);
+    q[i] = rsq_pos(x[i]);
   }
 }
 }  // namespace hydro
 
 extern "C" {
 
-int hydro_math_check(const double* x, int32_t n, double* recip_out, double* sqrt_out,
+int hydro_math_check(const double* x, int32_t n, double* recip_out, double* rsqrt_out,
                      void* stream) {
   g_err[0] = '\0';
   if (n < 0) return fail(HYDRO_EINVAL, "n %d < 0", n);
   if (n == 0) return HYDRO_OK;
-  if (!x || !recip_out || !sqrt_out) return fail(HYDRO_EINVAL, "NULL pointer");
+  if (!x || !recip_out || !rsqrt_out) return fail(HYDRO_EINVAL, "NULL pointer");
   hipLaunchKernelGGL(hydro::math_check_kernel, dim3((n + 255) / 256), dim3(256), 0,
-                     (hipStream_t)stream, x, n, recip_out, sqrt_out);
+                     (hipStream_t)stream, x, n, recip_out, rsqrt_out);
   HIP_TRY(hipGetLastError());
   return HYDRO_OK;
 }

@@ -36,23 +36,21 @@ __device__ __forceinline__ double recip(double x) {
   return fma(r, e, r);
 }
 
-// sqrt(y) for positive normal y by Goldschmidt's iteration (R. E.
-// Goldschmidt, M.Sc. thesis, MIT, 1964): from the hardware 1/sqrt estimate s
-// (relative error ~2^-24 on gfx950), g = y s approximates sqrt(y) and
-// h = s/2 approximates 1/(2 sqrt(y)); one coupled step with the residual
-// r = 1/2 - g h refines both (~2^-48), and a final Newton correction
-// g + h (y - g^2), with the residual y - g^2 taken exactly by a fused
-// multiply-add (Markstein 1990, above), squares the error again.  The GPU
-// tests bound the result against IEEE sqrt over 1e-17..1e3.
-__device__ __forceinline__ double sqrt_pos(double y) {
-  const double s = __builtin_amdgcn_rsq(y);
-  double g = y * s;
-  double h = 0.5 * s;
-  const double r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  h = fma(h, r, h);
-  const double d = fma(-g, g, y);
-  return fma(d, h, g);
+// 1/sqrt(y) for positive normal y: the hardware estimate refined by two
+// Newton-Raphson steps for the reciprocal square root, r <- r + (r/2)(1 - y r^2),
+// with the residual 1 - (y r) r taken by a fused multiply-add (the form of
+// Markstein 1990, above).  Each step squares the relative error of the
+// estimate; the GPU tests bound the result against the correctly rounded
+// 1/sqrt(y) over 1e-17..1e3.  Scaling y by 4^k scales the result by 2^-k
+// exactly (the estimate and every step commute with it).
+__device__ __forceinline__ double rsq_pos(double y) {
+  double r = __builtin_amdgcn_rsq(y);
+  double t = y * r;
+  double e = fma(-t, r, 1.0);
+  r = fma(0.5 * r, e, r);
+  t = y * r;
+  e = fma(-t, r, 1.0);
+  return fma(0.5 * r, e, r);
 }
 
 // Device-side descriptor: one per sub-grid in an aggregated launch.

@@ -129,8 +129,10 @@ __device__ __forceinline__ double core_flux(const double (&Wm)[5],
                                             double& wp) {
   const double vnm = ex * Wm[1] + ey * Wm[2] + ez * Wm[3];
   const double vnp = ex * Wp[1] + ey * Wp[2] + ez * Wp[3];
-  const double cm = sqrt_pos(kGamma * Wm[4] * recip(Wm[0]));
-  const double cp = sqrt_pos(kGamma * Wp[4] * recip(Wp[0]));
+  // sound speeds c = sqrt(gamma p / rho) = (gamma p) / sqrt(gamma p rho)
+  const double gm = kGamma * Wm[4], gpp = kGamma * Wp[4];
+  const double cm = gm * rsq_pos(gm * Wm[0]);
+  const double cp = gpp * rsq_pos(gpp * Wp[0]);
   const double ap = fmax(fmax(vnm + cm, vnp + cp), 0.0);
   const double am = fmin(fmin(vnm - cm, vnp - cp), 0.0);
   const double inv = recip(ap - am);

@@ -246,6 +246,11 @@ __device__ __forceinline__ void q4_step(const DevDesc& d, int group, double dt, 
   __syncthreads();   // tin holds every passive field; accumulator clear
 
   // ---- passive fields, one at a time, from LDS ---------------------------
+  // The march has no branch on the direction (the scheduler then overlaps
+  // positions): every lane forms U - lambda dF, which only the z lanes keep,
+  // and adds qa dF to the accumulator, qa = 0 for the z lanes (adding zero
+  // is exact, so the two x and y adds onto zero stay order-independent).
+  const double qa = dir == 2 ? 0.0 : 1.0;
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     double L[N];
@@ -269,10 +274,8 @@ __device__ __forceinline__ void q4_step(const DevDesc& d, int group, double dt, 
         const double Fh = wm[i - 5] * Wm[0] + wp[i - 5] * Wp[0];
         if (i >= 6) {
           const int cell = lbase + (i - 6) * lstride;
-          if (dir == 2)
-            L[i - 6] = tin[p * P + cell] - lambda * (Fh - Fprev);
-          else
-            atomicAdd(&acc[(p % 2) * P + cell], Fh - Fprev);
+          L[i - 6] = tin[p * P + cell] - lambda * (Fh - Fprev);
+          atomicAdd(&acc[(p % 2) * P + cell], qa * (Fh - Fprev));
         }
         Fprev = Fh;
       }

@@ -304,9 +304,10 @@ def hydro_step_each(descs, dt: float, dx: float, amax=None, stream=None) -> None
     _check(lib().hydro_step_each(arr, count, float(dt), float(dx), _ptr(amax), _stream(stream)))
 
 
-def math_check(x, recip_out, sqrt_out, stream=None) -> None:
-    """The kernels' reciprocal and square root on device arrays (diagnostic)."""
-    _check(lib().hydro_math_check(_ptr(x), int(x.numel()), _ptr(recip_out), _ptr(sqrt_out),
+def math_check(x, recip_out, rsqrt_out, stream=None) -> None:
+    """The kernels' reciprocal and reciprocal square root on device arrays
+    (diagnostic)."""
+    _check(lib().hydro_math_check(_ptr(x), int(x.numel()), _ptr(recip_out), _ptr(rsqrt_out),
                                   _stream(stream)))
 
 
