@@ -14,12 +14,17 @@
 // rule in both transverse directions, (16 F_centre + 4 sum F_edge + sum
 // F_vertex) / 36, summed in the fixed order s2 (outer), s1 (inner).
 //
-// One work-group of 512 lanes per sub-grid (one lane per interior cell; 256
-// registers per lane, no spills).  The lanes compute the 3 x 576 faces (9
-// points each, lines read from u_in through the caches, primitives recovered
-// per cell read) into an LDS face buffer; after a barrier each lane updates
-// its cell from its six faces (x, then y, then z differences, as the oracle
-// sums them) and writes U - lambda * sum.
+// One work-group of 576 lanes per sub-grid.  The hydro-core primitives of
+// the whole stored block (14^3 cells x 5) are recovered once into LDS.  The
+// faces are then taken one direction at a time, one lane per face (576 per
+// direction): the lane forms the 9 point states of the hydro core from LDS,
+// their central-upwind fluxes and the Simpson sum, keeping the 9 points'
+// passive-flux weights in registers; then it takes the passive fields one
+// after another, reading each field's 5-cell lines through the caches (the
+// work-group's reads at any time cover one field: ~22 KB per sub-grid, which
+// the caches hold).  The direction's face fluxes go to an LDS buffer; after a
+// barrier, lane t < 512 adds its cell's difference to its running sum (x,
+// then y, then z, as the oracle sums them).  Finally U_out = U - lambda sum.
 // Deterministic: no atomics, fixed summation orders.  The edge and corner
 // ghosts of u_in are read.
 #pragma once
@@ -29,8 +34,9 @@
 namespace hydro {
 
 struct S26 {
-  static constexpr int N = 8, M = 14, kThreads = 512, kFaces = 9 * 64;   // faces per direction
+  static constexpr int N = 8, M = 14, kThreads = 576, kFaces = 9 * 64;   // faces per direction
   static constexpr long FS = (long)M * M * M;
+  static constexpr int MMM = M * M * M;
 };
 
 // Right edge (toward +e) of the limited parabola of the middle of five
@@ -57,84 +63,100 @@ __device__ __forceinline__ void line5(int x, int y, int z, int e0, int e1, int e
     off[k] = ((z + (k - 2) * e2) * M + (y + (k - 2) * e1)) * M + (x + (k - 2) * e0);
 }
 
-// Hydro-core primitive state (rho, vx, vy, vz, p) of the cell at off[2]
-// toward the direction of its line.
-__device__ __forceinline__ void point_core(gcptr u, const int (&off)[5], double (&W)[5]) {
-  constexpr long FS = S26::FS;
-  double q[5][5];
+// Hydro-core state (rho, vx, vy, vz, p) of the cell at off[2] toward the
+// direction of its line, from the primitives staged in LDS.
+__device__ __forceinline__ void point_core(const double* __restrict__ prim, const int (&off)[5],
+                                           double (&W)[5]) {
+  constexpr int MMM = S26::MMM;
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    double U[5];
-#pragma unroll
-    for (int f = 0; f < 5; ++f) U[f] = u[f * FS + off[k]];
-    to_prim(U, q[k]);
-  }
-#pragma unroll
-  for (int f = 0; f < 5; ++f) W[f] = ppm_right5(q[0][f], q[1][f], q[2][f], q[3][f], q[4][f]);
+  for (int f = 0; f < 5; ++f)
+    W[f] = ppm_right5(prim[f * MMM + off[0]], prim[f * MMM + off[1]], prim[f * MMM + off[2]],
+                      prim[f * MMM + off[3]], prim[f * MMM + off[4]]);
 }
 
-// Passive field f (stored as is) of the cell at off[2] toward its line.
-__device__ __forceinline__ double point_passive(gcptr u, const int (&off)[5], int f) {
-  const gcptr p = u + f * S26::FS;
+// Passive field p (stored as is, the pointer at its first cell) of the cell
+// at off[2] toward its line.
+__device__ __forceinline__ double point_passive(gcptr p, const int (&off)[5]) {
   return ppm_right5(p[off[0]], p[off[1]], p[off[2]], p[off[3]], p[off[4]]);
 }
 
-
-
-// Face `face` of direction DIR (normal position i, transverse a, b): its
-// Simpson-integrated flux into fh[face * F ..]; returns the largest signal
-// speed of its 9 points.
-template <int DIR, int F>
-__device__ __forceinline__ double face26(gcptr u, int face, double* __restrict__ fh) {
+// Line offsets of point (s1, s2) of face `face` of direction DIR: om for
+// the cell below the face toward the point, op for the cell above.
+template <int DIR>
+__device__ __forceinline__ void face_lines(int face, int s1, int s2, int (&om)[5], int (&op)[5]) {
   constexpr int T1 = DIR == 0 ? 1 : 0, T2 = DIR == 2 ? 1 : 2;
-  constexpr double ex = DIR == 0 ? 1.0 : 0.0, ey = DIR == 1 ? 1.0 : 0.0, ez = DIR == 2 ? 1.0 : 0.0;
   const int i = face >> 6, a = face & 7, b = (face >> 3) & 7;
-  int lo[3];
+  int lo[3], em[3], ep[3];
   lo[DIR] = i + 2;
   lo[T1] = a + kGhost;
   lo[T2] = b + kGhost;
-  double sum[F];
+  em[DIR] = 1;
+  ep[DIR] = -1;
+  em[T1] = ep[T1] = s1;
+  em[T2] = ep[T2] = s2;
+  line5(lo[0], lo[1], lo[2], em[0], em[1], em[2], om);
+  line5(lo[0] + (DIR == 0), lo[1] + (DIR == 1), lo[2] + (DIR == 2), ep[0], ep[1], ep[2], op);
+}
+
+// Face `face` of direction DIR (normal position i, transverse a, b): its
+// Simpson-integrated flux into fh[face * F ..]; returns the largest signal
+// speed of its 9 points.  Points in the order s2 (outer), s1 (inner), weights
+// 16 (centre), 4 (edge midpoints), 1 (vertices), over 36.
+template <int DIR, int F>
+__device__ __forceinline__ double face26(const double* __restrict__ prim, gcptr u, int face,
+                                         double* __restrict__ fh) {
+  constexpr double ex = DIR == 0 ? 1.0 : 0.0, ey = DIR == 1 ? 1.0 : 0.0, ez = DIR == 2 ? 1.0 : 0.0;
+  double sum[5], wm[9], wp[9];
 #pragma unroll
-  for (int f = 0; f < F; ++f) sum[f] = 0.0;
+  for (int f = 0; f < 5; ++f) sum[f] = 0.0;
   double smax = 0.0;
-  // the 9 points one after another (unrolled, their loads would all be
-  // hoisted and spill)
-#pragma unroll 1
-  for (int s2 = -1; s2 <= 1; ++s2) {
-#pragma unroll 1
-    for (int s1 = -1; s1 <= 1; ++s1) {
-      int em[3], ep[3];
-      em[DIR] = 1;
-      ep[DIR] = -1;
-      em[T1] = ep[T1] = s1;
-      em[T2] = ep[T2] = s2;
-      int om[5], op[5];
-      line5(lo[0], lo[1], lo[2], em[0], em[1], em[2], om);
-      line5(lo[0] + (DIR == 0), lo[1] + (DIR == 1), lo[2] + (DIR == 2), ep[0], ep[1], ep[2], op);
-      double Wm[5], Wp[5], Fh[5], wm, wp;
-      point_core(u, om, Wm);
-      __builtin_amdgcn_sched_barrier(0);
-      point_core(u, op, Wp);
-      smax = fmax(smax, core_flux(Wm, Wp, ex, ey, ez, Fh, wm, wp));
-      const double w = (s1 == 0 && s2 == 0) ? 16.0 : (s1 == 0 || s2 == 0) ? 4.0 : 1.0;
+  // hydro core: the 9 points one after another (a scheduling barrier after
+  // each keeps the next point's LDS reads from being hoisted)
 #pragma unroll
-      for (int f = 0; f < 5; ++f) sum[f] = sum[f] + w * Fh[f];
-      // passive fields one at a time: flux w- q- + w+ q+ with the core's weights
+  for (int p = 0; p < 9; ++p) {
+    const int s1 = p % 3 - 1, s2 = p / 3 - 1;
+    int fc = face;   // opaque copy, as in the passive loop below
+    asm volatile("" : "+v"(fc));
+    int om[5], op[5];
+    face_lines<DIR>(fc, s1, s2, om, op);
+    double Wm[5], Wp[5], Fh[5];
+    point_core(prim, om, Wm);
+    __builtin_amdgcn_sched_barrier(0);
+    point_core(prim, op, Wp);
+    smax = fmax(smax, core_flux(Wm, Wp, ex, ey, ez, Fh, wm[p], wp[p]));
+    const double w = (s1 == 0 && s2 == 0) ? 16.0 : (s1 == 0 || s2 == 0) ? 4.0 : 1.0;
 #pragma unroll
-      for (int f = 5; f < F; ++f) {
-        __builtin_amdgcn_sched_barrier(0);
-        sum[f] = sum[f] + w * (wm * point_passive(u, om, f) + wp * point_passive(u, op, f));
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
+    for (int f = 0; f < 5; ++f) sum[f] = sum[f] + w * Fh[f];
+    __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
-  for (int f = 0; f < F; ++f) fh[face * F + f] = sum[f] * (1.0 / 36.0);
+  for (int f = 0; f < 5; ++f) fh[face * F + f] = sum[f] * (1.0 / 36.0);
+  // passive fields one at a time: flux w- q- + w+ q+ with each point's weights
+#pragma unroll 1
+  for (int f = 5; f < F; ++f) {
+    const gcptr pf = u + f * S26::FS;
+    double acc = 0.0;
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+      const int s1 = p % 3 - 1, s2 = p / 3 - 1;
+      // an opaque copy of the face index: the line offsets are recomputed
+      // at every point (a few integer ops) instead of being kept live from
+      // the hydro points through every field, which would spill them
+      int fc = face;
+      asm volatile("" : "+v"(fc));
+      int om[5], op[5];
+      face_lines<DIR>(fc, s1, s2, om, op);
+      const double w = (s1 == 0 && s2 == 0) ? 16.0 : (s1 == 0 || s2 == 0) ? 4.0 : 1.0;
+      acc = acc + w * (wm[p] * point_passive(pf, om) + wp[p] * point_passive(pf, op));
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    fh[face * F + f] = acc * (1.0 / 36.0);
+  }
   return smax;
 }
 
-// Face index within its direction of the face above (upper) and below
-// (lower) interior cell (cx, cy, cz) along DIR.
+// Face index within its direction of the face below interior cell
+// (cx, cy, cz) along DIR (the face above is 64 further).
 template <int DIR>
 __device__ __forceinline__ int face_below(int cx, int cy, int cz) {
   const int p = DIR == 0 ? cx : DIR == 1 ? cy : cz;
@@ -143,15 +165,32 @@ __device__ __forceinline__ int face_below(int cx, int cy, int cz) {
   return (p * 8 + b) * 8 + a;
 }
 
-// The fluxes of all 3 x 576 faces go to LDS (152 KB at 11 fields): lane t
-// computes faces t, t + 512, ... (at most 4), then lane t (one per interior
-// cell) updates its cell from its six faces, x then y then z.
+// One direction: every lane its face, then lane t < 512 (interior cell t)
+// adds the difference of its two faces to its running sum.
+template <int DIR, int F>
+__device__ __forceinline__ double step26_dir(const double* __restrict__ prim, gcptr u,
+                                             double* __restrict__ fh, int t, double (&sum)[F]) {
+  const double smax = face26<DIR, F>(prim, u, t, fh);
+  __syncthreads();   // the direction's face fluxes complete
+  if (t < 512) {
+    const int fl = face_below<DIR>(t & 7, (t >> 3) & 7, t >> 6);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      const double dF = fh[(fl + 64) * F + f] - fh[fl * F + f];
+      sum[f] = DIR == 0 ? dF : sum[f] + dF;
+    }
+  }
+  __syncthreads();   // read before the next direction writes
+  return smax;
+}
+
 template <int F>
 __global__ void __launch_bounds__(S26::kThreads)
     hydro_step26_kernel(const DevDesc* __restrict__ table, int count, double dt, double dx,
                         double* __restrict__ amax_out) {
-  constexpr int NF = 3 * S26::kFaces;
-  __shared__ double fh[NF * F];
+  constexpr int MMM = S26::MMM;
+  __shared__ double prim[5 * MMM];
+  __shared__ double fh[S26::kFaces * F];
   __shared__ double red[S26::kThreads / 64];
   constexpr int M = S26::M;
   const int s = blockIdx.x;
@@ -161,33 +200,30 @@ __global__ void __launch_bounds__(S26::kThreads)
   const int t = threadIdx.x;
   const double lambda = dt / ldexp(dx, -d.level);
 
-  double smax = 0.0;
-  for (int g = t; g < NF; g += S26::kThreads) {
-    const int dir = g / S26::kFaces, face = g - dir * S26::kFaces;
-    double* const out = fh + dir * S26::kFaces * F;
-    if (dir == 0)
-      smax = fmax(smax, face26<0, F>(u, face, out));
-    else if (dir == 1)
-      smax = fmax(smax, face26<1, F>(u, face, out));
-    else
-      smax = fmax(smax, face26<2, F>(u, face, out));
+  // hydro-core primitives of every stored cell
+  for (int c = t; c < MMM; c += S26::kThreads) {
+    double U[5], q[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) U[f] = u[f * S26::FS + c];
+    to_prim(U, q);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) prim[f * MMM + c] = q[f];
   }
   __syncthreads();
 
+  double sum[F];
+  double smax = step26_dir<0, F>(prim, u, fh, t, sum);
+  smax = fmax(smax, step26_dir<1, F>(prim, u, fh, t, sum));
+  smax = fmax(smax, step26_dir<2, F>(prim, u, fh, t, sum));
+
   // U_out = U - lambda * ((dF_x + dF_y) + dF_z), lane t = interior cell t
-  {
+  if (t < 512) {
     const int cx = t & 7, cy = (t >> 3) & 7, cz = t >> 6;
-    const int fx = face_below<0>(cx, cy, cz);
-    const int fy = S26::kFaces + face_below<1>(cx, cy, cz);
-    const int fz = 2 * S26::kFaces + face_below<2>(cx, cy, cz);
     const bool compact = d.compact != 0;
     const int gin = ((cz + kGhost) * M + (cy + kGhost)) * M + (cx + kGhost);
 #pragma unroll
     for (int f = 0; f < F; ++f) {
-      double sum = fh[(fx + 64) * F + f] - fh[fx * F + f];
-      sum = sum + (fh[(fy + 64) * F + f] - fh[fy * F + f]);
-      sum = sum + (fh[(fz + 64) * F + f] - fh[fz * F + f]);
-      const double v = u[f * S26::FS + gin] - lambda * sum;
+      const double v = u[f * S26::FS + gin] - lambda * sum[f];
       const long o = compact ? (long)f * 512 + t : f * S26::FS + gin;
       __builtin_nontemporal_store(v, &as_global(d.u_out)[o]);
     }
