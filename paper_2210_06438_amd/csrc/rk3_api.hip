@@ -80,6 +80,30 @@ int launch_fill(const hydro_brick_t& b, double* u, hipStream_t s) {
   return HYDRO_OK;
 }
 
+int launch_fill_faces(const hydro_brick_t& b, double* u, hipStream_t s) {
+  const hydro::BrickGeo g = geo_of(b);
+  const int parts = b.n == 8 ? hydro::kFaceParts<8> : b.n == 12 ? hydro::kFaceParts<12>
+                                                                 : hydro::kFaceParts<16>;
+  const dim3 grid((unsigned)brick_count(b), (unsigned)parts), block(256);
+  const bool f11 = b.nfields == 11;
+  switch (b.n) {
+    case 8:
+      if (f11) hipLaunchKernelGGL((hydro::ghost_fill_faces_kernel<8, 11>), grid, block, 0, s, u, u, g);
+      else hipLaunchKernelGGL((hydro::ghost_fill_faces_kernel<8, 6>), grid, block, 0, s, u, u, g);
+      break;
+    case 12:
+      if (f11) hipLaunchKernelGGL((hydro::ghost_fill_faces_kernel<12, 11>), grid, block, 0, s, u, u, g);
+      else hipLaunchKernelGGL((hydro::ghost_fill_faces_kernel<12, 6>), grid, block, 0, s, u, u, g);
+      break;
+    default:
+      if (f11) hipLaunchKernelGGL((hydro::ghost_fill_faces_kernel<16, 11>), grid, block, 0, s, u, u, g);
+      else hipLaunchKernelGGL((hydro::ghost_fill_faces_kernel<16, 6>), grid, block, 0, s, u, u, g);
+      break;
+  }
+  HIP_TRY(hipGetLastError());
+  return HYDRO_OK;
+}
+
 int launch_combine(const hydro_brick_t& b, double* out, const double* x, const double* y,
                    double a, double c, hipStream_t s) {
   const long M = b.n + 2 * HYDRO_GHOST;
@@ -122,20 +146,21 @@ namespace {
 //   1: w = E(u)                    (u = U0; w = U1)
 //   2: s = E(w); w = 3/4 u + 1/4 s (w = U2)
 //   3: s = E(w); u = 1/3 u + 2/3 s (u = U3)
-// each followed by the ghost fill of the buffer just formed.
+// each followed by the face-ghost fill of the buffer just formed (the
+// face-centre step reads no edge or corner ghost).
 int stage(hydro_rk3* rk, int k, double dt, double dx, double* amax, hipStream_t st) {
   int rc;
   if (k == 1) {
     if ((rc = hydro::api::plan_enqueue(rk->step_uw, dt, dx, amax, st))) return rc;
-    return launch_fill(rk->b, rk->w, st);
+    return launch_fill_faces(rk->b, rk->w, st);
   }
   if ((rc = hydro::api::plan_enqueue(rk->step_ws, dt, dx, nullptr, st))) return rc;
   if (k == 2) {
     if ((rc = launch_combine(rk->b, rk->w, rk->u, rk->s, 0.75, 0.25, st))) return rc;
-    return launch_fill(rk->b, rk->w, st);
+    return launch_fill_faces(rk->b, rk->w, st);
   }
   if ((rc = launch_combine(rk->b, rk->u, rk->u, rk->s, 1.0 / 3.0, 2.0 / 3.0, st))) return rc;
-  return launch_fill(rk->b, rk->u, st);
+  return launch_fill_faces(rk->b, rk->u, st);
 }
 
 int check_step_args(hydro_rk3* rk, double dt, double dx) {
@@ -164,6 +189,14 @@ int hydro_ghost_fill(const hydro_brick_t* brick, double* u, void* stream) {
   if (rc) return rc;
   if ((rc = check_buffer(u, "u"))) return rc;
   return launch_fill(*brick, u, (hipStream_t)stream);
+}
+
+int hydro_ghost_fill_faces(const hydro_brick_t* brick, double* u, void* stream) {
+  hydro::api::clear_error();
+  int rc = check_brick(brick);
+  if (rc) return rc;
+  if ((rc = check_buffer(u, "u"))) return rc;
+  return launch_fill_faces(*brick, u, (hipStream_t)stream);
 }
 
 int hydro_rk3_create(hydro_rk3_t** out, const hydro_brick_t* brick, double* u, double* w,

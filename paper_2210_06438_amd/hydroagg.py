@@ -174,6 +174,7 @@ def lib() -> ctypes.CDLL:
         L.hydro_get_tile.restype = ctypes.c_int
         BP = ctypes.POINTER(hydro_brick_t)
         L.hydro_ghost_fill.argtypes = [BP, ctypes.c_void_p, ctypes.c_void_p]
+        L.hydro_ghost_fill_faces.argtypes = [BP, ctypes.c_void_p, ctypes.c_void_p]
         L.hydro_rk3_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), BP, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p]
         L.hydro_rk3_stage.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
@@ -182,7 +183,8 @@ def lib() -> ctypes.CDLL:
             getattr(L, name).argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_void_p, ctypes.c_void_p]
         L.hydro_rk3_destroy.argtypes = [ctypes.c_void_p]
-        for name in ("hydro_ghost_fill", "hydro_rk3_create", "hydro_rk3_stage", "hydro_rk3_step",
+        for name in ("hydro_ghost_fill", "hydro_ghost_fill_faces", "hydro_rk3_create",
+                     "hydro_rk3_stage", "hydro_rk3_step",
                      "hydro_rk3_launch_graph", "hydro_rk3_destroy"):
             getattr(L, name).restype = ctypes.c_int
         L.hydro_math_check.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
@@ -325,6 +327,12 @@ def brick(n, nfields, nb, bc, level=0) -> hydro_brick_t:
 def ghost_fill(b: hydro_brick_t, u, stream=None) -> None:
     """Fill every ghost cell of the brick buffer u (in place)."""
     _check(lib().hydro_ghost_fill(ctypes.byref(b), _ptr(u), _stream(stream)))
+
+
+def ghost_fill_faces(b: hydro_brick_t, u, stream=None) -> None:
+    """Fill the face ghosts of the brick buffer u (in place); edge and corner
+    ghosts are left unchanged."""
+    _check(lib().hydro_ghost_fill_faces(ctypes.byref(b), _ptr(u), _stream(stream)))
 
 
 class RK3:
