@@ -163,6 +163,46 @@ def uneven_leg(args, torch, hydroagg, workloads, dev, stream):
     return res, tensors, dt, dx, groups
 
 
+def region_leg(args, torch, hydroagg, workloads, dev):
+    """Generic aggregation regions (Section V-D): independent host tasks, one
+    8^3 sub-grid each, from a pool of host threads.  Through a region, tasks
+    that arrive together form a team: one upload, one step launch and one
+    download per team.  The baseline has the same threads and tasks, one
+    hydro_step launch per task on the thread's stream.  Wall time of the
+    whole batch (hydro_region_drive)."""
+    count, nf, dt, dx = args.region_tasks, 11, 2e-3, 1.0 / 64
+    U = workloads.random_smooth(count, n=8, nfields=nf, seed=12)
+    u_in = torch.from_numpy(U).to(dev)
+    out = torch.empty((count, nf, 8, 8, 8), dtype=torch.float64, device=dev)
+    descs = hydroagg.subgrids(u_in, out)
+    rows = []
+    for threads in args.region_threads:
+        for mode, label in ((hydroagg.DRIVE_EACH, "one launch per task"),
+                            (hydroagg.DRIVE_REGION, "region")):
+            region = None
+            if mode == hydroagg.DRIVE_REGION:
+                region = hydroagg.Region(max_team=args.region_max_team, n_streams=2,
+                                         arena_bytes=1 << 20)
+            hydroagg.region_drive(region, (descs[0], min(count, 256)), dt, dx, threads, mode)
+            secs = []
+            for _ in range(args.region_reps):
+                secs.append(hydroagg.region_drive(region, descs, dt, dx, threads, mode))
+            row = {"mode": label, "threads": threads, "tasks": count,
+                   "seconds": round(statistics.median(secs), 5),
+                   "tasks_per_s": round(count / statistics.median(secs), 1)}
+            if region is not None:
+                st = region.stats()
+                region.close()
+                row["mean_team"] = round(st["tasks"] / max(st["teams"], 1), 2)
+                row["launches"] = st["launches"]
+            rows.append(row)
+            log(f"regions: {label}, {threads} threads: {row['tasks_per_s'] / 1e3:.1f}k tasks/s"
+                + (f", mean team {row['mean_team']}" if "mean_team" in row else ""))
+    return {"workload": f"{count} independent tasks, each one 8^3 sub-grid with 11 FP64 fields "
+                        "(random smooth), from a pool of host threads",
+            "max_team": args.region_max_team, "rows": rows}
+
+
 def timestep_leg(args, torch, hydroagg, workloads, dev, stream):
     """The paper's time-step shape (Table II: 512 sub-grids of 8^3 tiling a
     64^3 domain; three solver iterations per step, Section VI-A): one SSP-RK3
@@ -568,6 +608,12 @@ def main():
                     help="1: also time the step's access pattern without its arithmetic")
     ap.add_argument("--learned-splits", type=int, default=10)
     ap.add_argument("--no-timestep", action="store_true", help="skip the SSP-RK3 time-step leg")
+    ap.add_argument("--no-regions", action="store_true", help="skip the aggregation-region leg")
+    ap.add_argument("--region-tasks", type=int, default=4096)
+    ap.add_argument("--region-threads", type=lambda s: [int(x) for x in s.split(",")],
+                    default=[4, 16, 64])
+    ap.add_argument("--region-max-team", type=int, default=64)
+    ap.add_argument("--region-reps", type=int, default=3)
     ap.add_argument("--no-strategies", action="store_true", help="skip the strategy comparison leg")
     ap.add_argument("--step26-reps", type=int, default=10,
                     help="timed launches of the 26-point step (0: skip)")
@@ -779,6 +825,10 @@ def main():
     if not args.no_timestep:
         timestep = timestep_leg(args, torch, hydroagg, workloads, dev, stream)
 
+    regions = None
+    if not args.no_regions:
+        regions = region_leg(args, torch, hydroagg, workloads, dev)
+
     strategies = None
     if not args.no_strategies:
         strategies = strategies_leg(args, torch, hydroagg, workloads, dev, stream)
@@ -829,6 +879,7 @@ def main():
         "serving": serving,
         "learned_width": learned_res,
         "timestep": timestep,
+        "regions": regions,
         "strategies": strategies,
         "step26": step26,
         "tile_autotune": tiles,

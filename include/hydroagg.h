@@ -335,9 +335,14 @@ int hydro_rk3_destroy(hydro_rk3_t *rk);
  *                        the last caller's `args` (hipLaunchKernel style: an
  *                        array of pointers to each argument); the kernel finds
  *                        its member from its work-group index.
- *   hydro_region_leave   the last member records the team's completion;
+ *   hydro_region_wait    the last member records the team's completion;
  *                        every member returns when the team's device work has
- *                        finished (its downloaded chunks are then valid).
+ *                        finished.  Its downloaded chunks are then valid until
+ *                        it calls hydro_region_leave; only leave may follow.
+ *   hydro_region_leave   as hydro_region_wait if the team has not recorded
+ *                        its completion yet; when the last member has left,
+ *                        the team's slot and arena may serve the next team
+ *                        (read downloaded chunks between wait and leave).
  * Every member makes the same sequence of calls ("single GPU workload,
  * multiple tasks"); a call that differs from the team's (kind, bytes,
  * launch shape) fails the team with HYDRO_EINVAL, an arena overflow with
@@ -375,6 +380,7 @@ int hydro_region_download(hydro_region_t *r, const hydro_region_task_t *task,
 int hydro_region_launch(hydro_region_t *r, const hydro_region_task_t *task,
                         const void *kernel, uint32_t blocks_per_task,
                         uint32_t threads, uint32_t shmem, void **args);
+int hydro_region_wait(hydro_region_t *r, const hydro_region_task_t *task);
 int hydro_region_leave(hydro_region_t *r, const hydro_region_task_t *task);
 int hydro_region_stats(hydro_region_t *r, hydro_region_stats_t *out);
 int hydro_region_destroy(hydro_region_t *r);
@@ -404,6 +410,32 @@ typedef struct {
   int64_t n;
 } hydro_region_axpby_t;
 const void *hydro_region_kernel(int32_t which);
+
+/*
+ * hydro_region_drive -- many independent host tasks through a region, as
+ * the paper's tasks reach their kernel (Section V-D), for measurement:
+ * n_threads host threads (1..256, created and joined by the call) take the
+ * count tasks sg[0..count) in turn (count 1..2^20, every descriptor n = 8
+ * with one field count, 6 or 11).
+ *   mode HYDRO_DRIVE_REGION: each task enters region r, allocates a
+ *     descriptor chunk and an amax chunk, copies its descriptor, uploads,
+ *     launches the library's 8^3 step for the team, downloads, waits, reads
+ *     its amax and leaves: one upload, launch and download per team.
+ *   mode HYDRO_DRIVE_EACH: each task is one hydro_step launch of its own
+ *     sub-grid on its thread's stream, then a wait for its amax (the
+ *     non-aggregated baseline; r is not used and may be NULL).
+ * Every sub-grid is stepped exactly as hydro_step steps it (bitwise).
+ * amax_host (host, count doubles, or NULL) receives each task's amax;
+ * *seconds the wall time from the first thread's start to the last join.
+ * Errors: HYDRO_EINVAL for bad arguments; the first failing task's error
+ * otherwise (the other threads then stop taking tasks).  Allocates (threads,
+ * per-thread streams): set-up and measurement, not a step path.
+ */
+#define HYDRO_DRIVE_REGION 0
+#define HYDRO_DRIVE_EACH 1
+int hydro_region_drive(hydro_region_t *r, const hydro_subgrid_t *sg, int32_t count,
+                       int32_t n_threads, double dt, double dx, int32_t mode,
+                       double *amax_host, double *seconds);
 
 /*
  * Aggregator: explicit work aggregation of fine-grained sub-grid tasks (the

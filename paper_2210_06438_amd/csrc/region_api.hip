@@ -11,6 +11,11 @@
 
 #include <string.h>
 
+#include <string>
+
+#include <atomic>
+#include <chrono>
+#include <thread>
 #include <vector>
 
 #include "hydro_lds8.hpp"
@@ -240,6 +245,12 @@ int hydro_region_launch(hydro_region_t* r, const hydro_region_task_t* task, cons
   return core_rc(r->core->launch(to_core(task), kernel, blocks_per_task, threads, shmem, args));
 }
 
+int hydro_region_wait(hydro_region_t* r, const hydro_region_task_t* task) {
+  hydro::api::clear_error();
+  if (!r || !task) return fail(HYDRO_EINVAL, "NULL argument");
+  return core_rc(r->core->wait(to_core(task)));
+}
+
 int hydro_region_leave(hydro_region_t* r, const hydro_region_task_t* task) {
   hydro::api::clear_error();
   if (!r || !task) return fail(HYDRO_EINVAL, "NULL argument");
@@ -267,6 +278,106 @@ int hydro_region_destroy(hydro_region_t* r) {
   delete r->core;
   r->ex.teardown();
   delete r;
+  return HYDRO_OK;
+}
+
+// One task through the region: its descriptor in a team table, the team's
+// 8^3 step, its amax back (read between wait and leave).
+static int drive_region_task(hydro_region_t* r, const void* kernel, const hydro_subgrid_t& sg,
+                             double dt, double dx, double* amax) {
+  hydro_region_task_t t;
+  int rc = hydro_region_enter(r, &t);
+  if (rc) return rc;
+  int32_t bd = -1, ba = -1;
+  void *hd = nullptr, *dd = nullptr, *ha = nullptr, *da = nullptr;
+  void* base_d = nullptr;
+  void* base_a = nullptr;
+  uint64_t stride = 0;
+  int32_t size = t.size;
+  void* args[5] = {&base_d, &size, &dt, &dx, &base_a};
+  if (!(rc = hydro_region_alloc(r, &t, sizeof(hydro_subgrid_t), &bd, &hd, &dd)) &&
+      !(rc = hydro_region_alloc(r, &t, sizeof(double), &ba, &ha, &da))) {
+    memcpy(hd, &sg, sizeof sg);
+    if (!(rc = hydro_region_upload(r, &t, bd)) &&
+        !(rc = hydro_region_buffer(r, &t, bd, &base_d, &stride)) &&
+        !(rc = hydro_region_buffer(r, &t, ba, &base_a, &stride)) &&
+        !(rc = hydro_region_launch(r, &t, kernel, 1, hydro::Lds8::kThreads, 0, args)) &&
+        !(rc = hydro_region_download(r, &t, ba)) && !(rc = hydro_region_wait(r, &t)) && amax)
+      *amax = *(const double*)ha;
+  }
+  const int rl = hydro_region_leave(r, &t);   // every member leaves once
+  return rc ? rc : rl;
+}
+
+int hydro_region_drive(hydro_region_t* r, const hydro_subgrid_t* sg, int32_t count,
+                       int32_t n_threads, double dt, double dx, int32_t mode,
+                       double* amax_host, double* seconds) {
+  hydro::api::clear_error();
+  if (!sg || !seconds) return fail(HYDRO_EINVAL, "NULL argument");
+  if (mode != HYDRO_DRIVE_REGION && mode != HYDRO_DRIVE_EACH)
+    return fail(HYDRO_EINVAL, "mode %d", mode);
+  if (mode == HYDRO_DRIVE_REGION && !r) return fail(HYDRO_EINVAL, "region is NULL");
+  if (count < 1 || count > (1 << 20)) return fail(HYDRO_EINVAL, "count %d", count);
+  if (n_threads < 1 || n_threads > 256) return fail(HYDRO_EINVAL, "n_threads %d", n_threads);
+  if (!(dt >= 0.0) || !(dx > 0.0)) return fail(HYDRO_EINVAL, "dt >= 0 and dx > 0 required");
+  const int nf = sg[0].nfields;
+  for (int32_t i = 0; i < count; ++i)
+    if (sg[i].n != 8 || sg[i].nfields != nf || (nf != 6 && nf != 11))
+      return fail(HYDRO_EINVAL, "task %d: n=%d nfields=%d (n = 8, one field count of 6 or 11)",
+                  i, sg[i].n, sg[i].nfields);
+  const void* kernel = hydro_region_kernel(nf == 11 ? HYDRO_REGION_STEP8_F11 : HYDRO_REGION_STEP8_F6);
+  std::atomic<int32_t> next{0};
+  std::atomic<int> first_rc{HYDRO_OK};
+  std::vector<std::string> errs((size_t)n_threads);
+  auto worker = [&](int w) {
+    hipStream_t st = nullptr;
+    double* dev_amax = nullptr;
+    double* pinned = nullptr;
+    if (mode == HYDRO_DRIVE_EACH) {
+      if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+          hipMalloc((void**)&dev_amax, sizeof(double)) != hipSuccess ||
+          hipHostMalloc((void**)&pinned, sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        int z = HYDRO_OK;
+        first_rc.compare_exchange_strong(z, HYDRO_EHIP);
+        errs[w] = "per-thread stream or buffers";
+      }
+    }
+    while (first_rc.load() == HYDRO_OK) {
+      const int32_t i = next.fetch_add(1);
+      if (i >= count) break;
+      double a = 0.0;
+      int rc;
+      if (mode == HYDRO_DRIVE_REGION) {
+        rc = drive_region_task(r, kernel, sg[i], dt, dx, &a);
+      } else {
+        rc = hydro_step(&sg[i], 1, dt, dx, dev_amax, st);
+        if (!rc && (hipMemcpyAsync(pinned, dev_amax, sizeof(double), hipMemcpyDeviceToHost, st) !=
+                        hipSuccess || hipStreamSynchronize(st) != hipSuccess))
+          rc = HYDRO_EHIP;
+        a = rc ? 0.0 : *pinned;
+      }
+      if (rc) {
+        int z = HYDRO_OK;
+        if (first_rc.compare_exchange_strong(z, rc)) errs[w] = hydro_last_error();
+        break;
+      }
+      if (amax_host) amax_host[i] = a;
+    }
+    if (pinned) (void)hipHostFree(pinned);
+    if (dev_amax) (void)hipFree(dev_amax);
+    if (st) (void)hipStreamDestroy(st);
+  };
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<std::thread> ts;
+  for (int w = 0; w < n_threads; ++w) ts.emplace_back(worker, w);
+  for (auto& th : ts) th.join();
+  *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  const int rc = first_rc.load();
+  if (rc) {
+    for (auto& e : errs)
+      if (!e.empty()) return fail(rc, "%s", e.c_str());
+    return fail(rc, "a task failed");
+  }
   return HYDRO_OK;
 }
 

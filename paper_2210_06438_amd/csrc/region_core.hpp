@@ -24,13 +24,18 @@
 //     a launch's grid is size x blocks_per_task work-groups and its
 //     arguments are those of the last caller (they name team buffers, which
 //     are the same for every member);
-//   * leave(): the last member records the team's completion on the
+//   * wait(): the last member records the team's completion on the
 //     executor; every member returns when the team's device work is done.
+//     Its downloaded chunks are then valid until it leaves; only leave()
+//     may follow;
+//   * leave(): as wait() if the team has not recorded its completion yet;
+//     when the last member has left, the team's slot (and its arena) may be
+//     reused by the next team.
 // A member whose k-th call differs from the team's k-th operation (another
 // kind or size) is an error (kMismatch), as is an arena overflow (kNoSpace):
 // either fails the whole team -- every member's later calls return that
 // error and nothing more is launched for it -- and wakes the members waiting
-// in leave().  Every member must still call leave() once, which frees the
+// in wait() or leave().  Every member must still call leave() once, which frees the
 // team's slot when the last one has.
 //
 // Exec (the HIP streams in region_api.hip, a fake in the CPU test); team
@@ -73,7 +78,7 @@ struct RegionStats {
 template <class Exec>
 class RegionCore {
  public:
-  enum Kind { kAlloc, kUpload, kLaunch, kDownload, kLeave };
+  enum Kind { kAlloc, kUpload, kLaunch, kDownload, kWait, kLeave };
 
   static constexpr int kSlotsPerStream = 2;
 
@@ -152,24 +157,17 @@ class RegionCore {
     return ex_.launch(t.team, kernel, blocks_per_task * (unsigned)tm.size, threads, shmem, args);
   }
 
+  int wait(const RegionTask& t) {
+    std::unique_lock<std::mutex> lk(mu_);
+    if (!valid(t)) return kMismatch;
+    return complete(lk, slots_[t.team], t, kWait);
+  }
+
   int leave(const RegionTask& t) {
     std::unique_lock<std::mutex> lk(mu_);
     if (!valid(t)) return kMismatch;
     Team& tm = slots_[t.team];
-    Op* op = next_op(tm, t, kLeave, 0);
-    int rc = op ? kRegionOk : tm.err;
-    if (op && op->arrived == tm.size) {
-      rc = ex_.record(t.team, tm.id);
-      tm.recorded = true;
-      cv_.notify_all();
-    }
-    while (!tm.recorded) cv_.wait(lk);
-    const uint64_t id = tm.id;
-    const bool marked = !tm.err;
-    lk.unlock();
-    const int w = marked ? ex_.wait(t.team, id) : kRegionOk;
-    lk.lock();
-    if (!rc) rc = tm.err ? tm.err : w;
+    const int rc = complete(lk, tm, t, kLeave);
     if (++tm.left == tm.size) {
       tm.active = false;   // slot reusable: its device work is done
       cv_.notify_all();
@@ -196,6 +194,8 @@ class RegionCore {
     int size = 0, stream = 0, nbuf = 0, left = 0;
     int err = kRegionOk;   // the team's failure, if any
     bool recorded = false;
+    bool waiting = false, done = false;   // one member waits on the executor
+    int wait_rc = kRegionOk;
     uint64_t used = 0;
     std::vector<Op> ops;
     std::vector<int> next;   // next op index of each member
@@ -235,6 +235,10 @@ class RegionCore {
   Op* next_op(Team& tm, const RegionTask& t, Kind k, uint64_t arg) {
     const int pos = tm.next[t.index]++;
     if (tm.err) return nullptr;
+    if (tm.recorded && k != kLeave) {   // only leave() follows the completion
+      fail_team(tm, kMismatch);
+      return nullptr;
+    }
     if (pos == (int)tm.ops.size()) tm.ops.push_back(Op{k, arg});
     Op& op = tm.ops[pos];
     if (op.kind != k || op.arg != arg) {
@@ -243,6 +247,37 @@ class RegionCore {
     }
     op.arrived++;
     return &op;
+  }
+
+  // wait() and leave(): the last member to arrive records the team's
+  // completion (unless a wait() already has).  One member then waits for it
+  // on the executor; the others wait for that member (one runtime wait per
+  // team, not one per member).  Under mu_ (released while waiting).
+  int complete(std::unique_lock<std::mutex>& lk, Team& tm, const RegionTask& t, Kind k) {
+    Op* op = next_op(tm, t, k, 0);
+    int rc = op ? kRegionOk : tm.err;
+    if (op && op->arrived == tm.size && !tm.recorded) {
+      rc = ex_.record(t.team, tm.id);
+      tm.recorded = true;
+      cv_.notify_all();
+    }
+    while (!tm.recorded) cv_.wait(lk);
+    if (!tm.err && !tm.done) {
+      if (!tm.waiting) {
+        tm.waiting = true;
+        const uint64_t id = tm.id;
+        lk.unlock();
+        const int w = ex_.wait(t.team, id);
+        lk.lock();
+        tm.wait_rc = w;
+        tm.done = true;
+        cv_.notify_all();
+      } else {
+        while (!tm.done) cv_.wait(lk);
+      }
+    }
+    if (!rc) rc = tm.err ? tm.err : tm.wait_rc;
+    return rc;
   }
 
   int transfer(const RegionTask& t, int32_t b, Kind k) {

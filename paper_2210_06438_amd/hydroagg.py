@@ -91,6 +91,7 @@ class hydro_region_axpby_t(ctypes.Structure):
 
 
 REGION_STEP8_F6, REGION_STEP8_F11, REGION_AXPBY = 0, 1, 2
+DRIVE_REGION, DRIVE_EACH = 0, 1
 
 _lib = None
 
@@ -142,13 +143,17 @@ def lib() -> ctypes.CDLL:
         L.hydro_region_download.argtypes = [VP, RT, ctypes.c_int32]
         L.hydro_region_launch.argtypes = [VP, RT, VP, ctypes.c_uint32, ctypes.c_uint32,
                                           ctypes.c_uint32, ctypes.POINTER(VP)]
+        L.hydro_region_wait.argtypes = [VP, RT]
         L.hydro_region_leave.argtypes = [VP, RT]
+        L.hydro_region_drive.argtypes = [VP, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_double)]
         L.hydro_region_stats.argtypes = [VP, ctypes.POINTER(hydro_region_stats_t)]
         L.hydro_region_destroy.argtypes = [VP]
         for name in ("hydro_region_create", "hydro_region_enter", "hydro_region_alloc",
                      "hydro_region_buffer", "hydro_region_upload", "hydro_region_download",
-                     "hydro_region_launch", "hydro_region_leave", "hydro_region_stats",
-                     "hydro_region_destroy"):
+                     "hydro_region_launch", "hydro_region_wait", "hydro_region_leave",
+                     "hydro_region_stats", "hydro_region_destroy", "hydro_region_drive"):
             getattr(L, name).restype = ctypes.c_int
         L.hydro_region_kernel.argtypes = [ctypes.c_int32]
         L.hydro_region_kernel.restype = VP
@@ -408,6 +413,25 @@ class Plan:
             pass
 
 
+def region_drive(region, descs, dt: float, dx: float, n_threads: int, mode: int,
+                 amax=None) -> float:
+    """hydro_region_drive: the tasks of `descs` (subgrids()) from n_threads
+    host threads, through `region` (DRIVE_REGION) or one hydro_step launch
+    each (DRIVE_EACH; region may be None).  amax: a float64 numpy array of
+    one value per task, filled in place, or None.  Returns the wall time in
+    seconds."""
+    arr, count = descs
+    secs = ctypes.c_double()
+    ap = None
+    if amax is not None:
+        assert amax.dtype.name == "float64" and amax.size == count and amax.flags["C_CONTIGUOUS"]
+        ap = amax.ctypes.data
+    _check(lib().hydro_region_drive(region._h if region is not None else None, arr, int(count),
+                                    int(n_threads), float(dt), float(dx), int(mode), ap,
+                                    ctypes.byref(secs)))
+    return secs.value
+
+
 def region_kernel(which: int) -> int:
     """Address of a library kernel usable inside a region (REGION_*)."""
     k = lib().hydro_region_kernel(int(which))
@@ -460,6 +484,15 @@ class Region:
             *[ctypes.cast(ctypes.pointer(a), ctypes.c_void_p) for a in args])
         _check(lib().hydro_region_launch(self._h, ctypes.byref(task), kernel, int(blocks_per_task),
                                          int(threads), int(shmem), ptrs))
+
+    def wait(self, task) -> None:
+        """Until the team's device work is done; downloaded chunks are then
+        valid until leave()."""
+        _check(lib().hydro_region_wait(self._h, ctypes.byref(task)))
+
+    def drive(self, descs, dt: float, dx: float, n_threads: int, amax=None) -> float:
+        """hydro_region_drive through this region: seconds of wall time."""
+        return region_drive(self, descs, dt, dx, n_threads, DRIVE_REGION, amax)
 
     def leave(self, task) -> None:
         _check(lib().hydro_region_leave(self._h, ctypes.byref(task)))

@@ -81,7 +81,7 @@ struct FakeExec {
 using R = RegionCore<FakeExec>;
 
 // One task through the whole region: its chunk holds (its value, 0); after
-// the team's launch and download it must read (value + 1000, 1000).
+// the team's launch, download and wait it must read (value + 1000, 1000).
 static int run_task(R& r, uint64_t value, RegionTask* seat, std::promise<void>* hold = nullptr,
                     std::shared_future<void>* gate = nullptr) {
   RegionTask t;
@@ -103,10 +103,11 @@ static int run_task(R& r, uint64_t value, RegionTask* seat, std::promise<void>* 
   void* args[1] = {&words};
   if ((rc = r.launch(t, nullptr, 3, 64, 0, args))) return rc;
   if ((rc = r.download(t, b))) return rc;
+  if ((rc = r.wait(t))) return rc;
+  CHECK(((uint64_t*)h)[0] == value + 1000 && ((uint64_t*)h)[1] == 1000);
   if ((rc = r.leave(t))) return rc;
   CHECK(stride == 16);
   CHECK(d == base + t.index * 16);
-  CHECK(((uint64_t*)h)[0] == value + 1000 && ((uint64_t*)h)[1] == 1000);
   return 0;
 }
 
@@ -116,7 +117,7 @@ static void single_task() {
   RegionTask t;
   CHECK(run_task(r, 7, &t) == 0);
   CHECK(t.size == 1 && t.index == 0);
-  // upload, launch (3 blocks of 64), download, record: once each
+  // upload, launch (3 blocks of 64), download, record (at wait): once each
   CHECK(ex.calls.size() == 4);
   CHECK(ex.calls[0].what == 'u' && ex.calls[0].a == 0 && ex.calls[0].b == 16);
   CHECK(ex.calls[1].what == 'l' && ex.calls[1].a == 3 && ex.calls[1].b == 64);
@@ -236,6 +237,30 @@ static void chunk_strides() {
   CHECK(r.leave(t) == 0);
 }
 
+// wait() records the completion once; leave() after it records nothing
+// more; any other call after wait() fails the team.
+static void wait_then_leave() {
+  FakeExec ex(1);
+  R r(ex, 4);
+  RegionTask t;
+  CHECK(r.enter(&t) == 0);
+  int32_t b;
+  char *h, *d;
+  CHECK(r.alloc(t, 8, &b, &h, &d) == 0);
+  CHECK(r.wait(t) == 0);
+  CHECK(r.leave(t) == 0);
+  int records = 0;
+  for (auto& c : ex.calls) records += c.what == 'r';
+  CHECK(records == 1);
+  RegionTask u;
+  CHECK(r.enter(&u) == 0);
+  CHECK(r.alloc(u, 8, &b, &h, &d) == 0);
+  CHECK(r.wait(u) == 0);
+  CHECK(r.download(u, b) == hydro::kMismatch);   // after the completion marker
+  CHECK(r.leave(u) == hydro::kMismatch);
+  CHECK(run_task(r, 3, &t) == 0);                 // slot freed
+}
+
 static void arena_overflow() {
   FakeExec ex(1, 1024);
   R r(ex, 4);
@@ -256,6 +281,7 @@ int main() {
   teams_from_threads();
   mismatch_fails_the_team();
   chunk_strides();
+  wait_then_leave();
   arena_overflow();
   if (g_fail) {
     printf("%d checks failed\n", (int)g_fail);

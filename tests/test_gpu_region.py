@@ -3,7 +3,9 @@ each step one sub-grid through a region -- a descriptor chunk and an amax
 chunk of shared team buffers, one upload, one launch of the library's step
 kernel and one download per team -- get bitwise the result and amax of
 hydro_step; the first task holds its team open so that a full team queues
-behind it.  The auxiliary kernel (a x + b y per member) runs the same way."""
+behind it.  The auxiliary kernel (a x + b y per member) runs the same way.
+The library's task driver steps a batch from many threads through a region
+and as one launch per task, both bitwise hydro_step."""
 import ctypes
 import threading
 import time
@@ -88,8 +90,9 @@ def test_threads_step_subgrids_through_a_region(dev):
                                               ctypes.c_double(dt), ctypes.c_double(dx),
                                               ctypes.c_void_p(base_a)])
             region.download(t, ba)
+            region.wait(t)
+            amax[i] = ctypes.c_double.from_address(ha).value   # valid until leave
             region.leave(t)
-            amax[i] = ctypes.c_double.from_address(ha).value
         return run
     _run_threads([task(i) for i in range(count)], hold, region, seated_tasks=9)
     st = region.stats()
@@ -135,3 +138,40 @@ def test_auxiliary_kernel_in_a_region(dev):
         want = coef[i][0] * xs[i].cpu().numpy() + coef[i][1] * ys[i].cpu().numpy()
         got = outs[i].cpu().numpy()
         assert np.max(np.abs(got - want)) <= 1e-15 * np.max(np.abs(want)), i
+
+
+@pytest.mark.parametrize("mode", ["region", "each"])
+def test_task_driver_matches_hydro_step(dev, mode):
+    count, nf, dt, dx = 512, 11, 0.002, 0.05
+    print(f"region driver: {count} tasks, 16 threads, mode {mode}", flush=True)
+    U = workloads.random_smooth(count, n=8, nfields=nf, seed=813)
+    u_in = torch.from_numpy(U).to(dev)
+    ref_out = torch.full((count, nf, 8, 8, 8), float("nan"), dtype=torch.float64, device=dev)
+    ref_amax = torch.zeros(count, dtype=torch.float64, device=dev)
+    hydroagg.hydro_step(hydroagg.subgrids(u_in, ref_out), dt, dx, ref_amax)
+    torch.cuda.synchronize()
+    out = torch.full_like(ref_out, float("nan"))
+    amax = np.zeros(count)
+    region = hydroagg.Region(max_team=64, n_streams=2, arena_bytes=1 << 16) if mode == "region" else None
+    secs = hydroagg.region_drive(region, hydroagg.subgrids(u_in, out), dt, dx, 16,
+                                 hydroagg.DRIVE_REGION if mode == "region" else hydroagg.DRIVE_EACH,
+                                 amax)
+    torch.cuda.synchronize()
+    if region is not None:
+        st = region.stats()
+        region.close()
+        print(f"  {secs * 1e3:.1f} ms, stats {st}", flush=True)
+        assert st["tasks"] == count and st["launches"] == st["teams"] <= count
+    assert np.array_equal(out.cpu().numpy(), ref_out.cpu().numpy())
+    assert np.array_equal(amax, ref_amax.cpu().numpy())
+
+
+def test_task_driver_rejects_bad_arguments(dev):
+    U = workloads.random_smooth(2, n=8, nfields=11, seed=814)
+    u_in = torch.from_numpy(U).to(dev)
+    out = torch.empty((2, 11, 8, 8, 8), dtype=torch.float64, device=dev)
+    d = hydroagg.subgrids(u_in, out)
+    with pytest.raises(hydroagg.HydroError):
+        hydroagg.region_drive(None, d, 0.001, 0.05, 4, hydroagg.DRIVE_REGION)   # no region
+    with pytest.raises(hydroagg.HydroError):
+        hydroagg.region_drive(None, d, 0.001, 0.05, 0, hydroagg.DRIVE_EACH)     # no threads
