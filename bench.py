@@ -363,7 +363,28 @@ def step26_leg(args, torch, hydroagg, u_in, u_out, dt, dx, count, n, nf, stream)
                     "Simpson's rule over each face; one launch (descriptor copy included)",
             "ms_per_step": round(ms, 4), "value": round(cells / (ms * 1e-3), 1),
             "unit": "cell-updates/s", "flux_points_per_step": count * 3 * 9 * (n + 1) * n * n,
-            "reps": args.step26_reps}
+            "reps": args.step26_reps,
+            "roofline": step26_roofline(hydroagg.version(), ms, count, n, nf)}
+
+
+def step26_roofline(version, ms, count, n, nf):
+    """The 26-point kernel is bound by vector ALU issue, not HBM (traffic
+    1.4x its tile bytes in the committed profile): FP64 FLOP per launch and
+    VALU instructions from the committed SQ counter record of this kernel
+    build and workload (null otherwise), against the FP64 vector peak and
+    against the issue time of those instructions on 256 CUs x 4 SIMDs at
+    2.4 GHz (4 cycles per wave instruction)."""
+    rec = counter_record("measured_fp64_step26.json", version,
+                         f"{count}x{n}^3 F={nf} interior-out, 26-point form",
+                         f"hydro_step26_kernel<{nf}>")
+    if rec is None:
+        return None
+    tflops = float(rec["fp64_flop_per_launch"]) / (ms * 1e-3) / 1e12
+    issue_ms = (float(rec["valu_insts_per_wave"]) * float(rec["waves_per_launch"]) * 4
+                / (256 * 4 * 2.4e9) * 1e3)
+    return {"bound": "alu", "achieved": round(tflops, 2), "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(tflops / FP64_PEAK_TFLOPS, 4),
+            "valu_issue_ms": round(issue_ms, 3), "valu_issue_frac": round(issue_ms / ms, 3)}
 
 
 def _time_oracle(oracle, U, dt, dx, threads, seconds, levels=None, reps=2):
