@@ -13,8 +13,10 @@
 // of 4 with idle slots) are 2, 7 or 16 work-groups whose indices are equal
 // modulo 8, so they run on one XCD and share its L2 for their common halos.
 //
-// Direction sums as in hydro_lds8.hpp: exactly two LDS atomic adds onto zero
-// per cell (x and y lanes), the z lanes keep U - lambda dF_z.  Every block
+// Direction sums as in hydro_lds8.hpp: for the hydro core exactly two LDS
+// atomic adds onto zero per cell (x and y lanes), the z lanes keep
+// U - lambda dF_z; the passive fields in groups of three with plain stores
+// and a finalization shared by the work-group.  Every block
 // owns all of its cells; amax is combined across blocks with an atomic max of
 // the bit pattern onto a slot zeroed before the launch.
 #pragma once
@@ -112,6 +114,36 @@ __device__ __forceinline__ void q4_load_ghosts(const double* __restrict__ src, i
     for (int j = 0; j < 6; ++j) {
       const int i = j < 3 ? j : j + Q4::N;
       g[f][j] = p[f * Frame<MP>::FS + i * gstride];
+    }
+  }
+}
+
+// Finalize `count` (<= 3) passive fields of the four blocks, from field
+// `kfirst` on, shared by all lanes (lane t takes elements t, t + 192, ...
+// of the fields stacked [r][q][z][y][x]): U_out = Z - lambda * (X + Y), Z
+// the z lanes' U - lambda dF_z (zr region r), X and Y the x and y flux
+// differences (acc and held region r).  Idle block slots store nothing.
+template <int MP>
+__device__ __forceinline__ void q4_finalize(const double* __restrict__ zr,
+                                            const double* __restrict__ acc,
+                                            const double* __restrict__ held, int kfirst,
+                                            int count, double lambda, double* __restrict__ uout,
+                                            bool compact, long ofs, int group, int t) {
+  constexpr int NI = Q4Grid<MP>::NI;
+  constexpr int P = Q4::P;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {   // 3 fields x 256 cells / 192 lanes
+    const int e = t + j * Q4::kThreads;
+    const int r = e >> 8, q = (e >> 6) & 3, x = e & 3, y = (e >> 2) & 3, z = (e >> 4) & 3;
+    const int item = 4 * group + q;
+    if (r < count && item < Q4Grid<MP>::kBlocks) {
+      const int lc = r * P + q4cell(q, x, y, z);
+      const double v = zr[lc] - lambda * (acc[lc] + held[lc]);
+      int bx, by, bz;
+      const int org = q4_org<MP>(item, bx, by, bz);
+      const long o = compact ? ((long)(4 * bz + z) * NI + 4 * by + y) * NI + 4 * bx + x
+                             : (long)org + Frame<MP>::cell(x, y, z);
+      __builtin_nontemporal_store(v, &as_global(uout)[(kfirst + r) * ofs + o]);
     }
   }
 }
@@ -238,22 +270,28 @@ __device__ __forceinline__ void q4_step(const DevDesc& d, int group, double dt, 
         if (stores)
           __builtin_nontemporal_store(held[cell] - lambda * acc[cell],
                                       &as_global(uout)[k * ofs + obase + c * ostride]);
-        acc[cell] = 0.0;
       }
     }
   }
   q4_store_share<NP>(tin, t, ps);
-  __syncthreads();   // tin holds every passive field; accumulator clear
+  __syncthreads();   // tin holds every passive field; the hydro sums are read
 
-  // ---- passive fields, one at a time, from LDS ---------------------------
-  // The march has no branch on the direction (the scheduler then overlaps
-  // positions): every lane forms U - lambda dF, which only the z lanes keep,
-  // and adds qa dF to the accumulator, qa = 0 for the z lanes (adding zero
-  // is exact, so the two x and y adds onto zero stay order-independent).
-  const double qa = dir == 2 ? 0.0 : 1.0;
+  // ---- passive fields from LDS, in groups of at most 3 -------------------
+  // As in hydro_lds8.hpp: within a group every lane marches its line for
+  // each field in turn, with no barrier between fields, no atomics and no
+  // branch on the direction: it stores fma(pa, dF, pz u) -- the x lanes dF
+  // to acc region r, the y lanes dF to held region r, the z lanes
+  // u - lambda dF to tin region NP + r.  One barrier then lets every lane
+  // finalize a share of the group's cells of the four blocks.
+  constexpr int G = NP < 3 ? NP : 3;
+  static_assert((NP + G) * P <= 6 * Lds8::P && G * P <= 5 * Lds8::P,
+                "q4 passive regions exceed the LDS arrays");
+  const double pa = dir == 2 ? -lambda : 1.0;
+  const double pz = dir == 2 ? 1.0 : 0.0;
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
-    double L[N];
+    const int r = p % G;
+    double* const dst = dir == 0 ? acc + r * P : dir == 1 ? held + r * P : tin + (NP + r) * P;
     Recon<1> rc;
     double Fprev = 0.0;
     double qv[1], Wm[1], Wp[1];
@@ -274,23 +312,16 @@ __device__ __forceinline__ void q4_step(const DevDesc& d, int group, double dt, 
         const double Fh = wm[i - 5] * Wm[0] + wp[i - 5] * Wp[0];
         if (i >= 6) {
           const int cell = lbase + (i - 6) * lstride;
-          L[i - 6] = tin[p * P + cell] - lambda * (Fh - Fprev);
-          atomicAdd(&acc[(p % 2) * P + cell], qa * (Fh - Fprev));
+          dst[cell] = fma(pa, Fh - Fprev, pz * tin[p * P + cell]);
         }
         Fprev = Fh;
       }
     }
-    // Two accumulator regions alternate, as in hydro_lds8.hpp.
-    __syncthreads();
-    if (dir == 2) {
-#pragma unroll
-      for (int c = 0; c < N; ++c) {
-        const int cell = (p % 2) * P + lbase + c * lstride;
-        if (stores)
-          __builtin_nontemporal_store(L[c] - lambda * acc[cell],
-                                      &as_global(uout)[(5 + p) * ofs + obase + c * ostride]);
-        acc[cell] = 0.0;
-      }
+    if (r == G - 1 || p == NP - 1) {
+      __syncthreads();   // the group's differences are in LDS
+      q4_finalize<MP>(tin + NP * P, acc, held, 5 + p - r, r + 1, lambda, uout, compact, ofs,
+                      group, t);
+      if (p < NP - 1) __syncthreads();   // read before the next group writes
     }
   }
 
