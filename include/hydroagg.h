@@ -272,24 +272,30 @@ int hydro_ghost_fill_faces(const hydro_brick_t *brick, double *u, void *stream);
  * three-stage strong-stability-preserving Runge-Kutta method of Shu and
  * Osher (J. Comput. Phys. 77, 1988), with E(V) = one hydro_step stage of V:
  *   U1 = E(U0),  U2 = 3/4 U0 + 1/4 E(U1),  U3 = 1/3 U0 + 2/3 E(U2),
+ * each combination rounded as a x + b y with the two products and the sum
+ * rounded once (for n = 8 formed in the step's own stores),
  * each stage's result with its face ghosts refilled (hydro_ghost_fill_faces:
  * the stage reads no edge or corner ghost) before the next stage reads it.
  * hydro_rk3_create binds the brick to three caller-owned device brick
  * buffers: u (the state, with face ghosts filled on entry; it holds U3,
  * face ghosts filled, after a step; its edge and corner ghosts are left as
- * they were) and two work buffers w and s (their contents are overwritten); it creates the plans of the two aggregated steps (E(u) into
- * w, E(w) into s), so it allocates and belongs to set-up.  The buffers must
- * not overlap and must stay alive until hydro_rk3_destroy.
- * hydro_rk3_stage(rk, k, ...) runs stage k = 1, 2 or 3 alone (after stage 1
- * and 2, w holds U1 and U2 with face ghosts; after stage 3, u holds U3), so that
+ * they were) and two work buffers w and s (their contents are
+ * overwritten).  It creates the stages' aggregated steps (E(u) into w, E(w)
+ * into s, E(s) into u for n = 8 or into w otherwise) and their descriptor
+ * tables, so it allocates and belongs to set-up.  The buffers must not
+ * overlap and must stay alive until hydro_rk3_destroy.
+ * hydro_rk3_stage(rk, k, ...) runs stage k = 1, 2 or 3 alone (after stage 1,
+ * w holds U1; after stage 2, s holds U2; after stage 3, u holds U3; each
+ * with face ghosts), so that
  * the three calls in order are one time-step; hydro_rk3_step runs all three
  * as launches, hydro_rk3_launch_graph as ONE hipGraph launch (captured at
  * first use and again when dt, dx or amax_dev change; results bitwise those
  * of hydro_rk3_step).  dt >= 0 and dx > 0 as in hydro_step; amax_dev (device,
  * one double per sub-grid, or NULL) receives the amax of stage 1, i.e. of
  * the state the step starts from (hydro_step's definition); the later stages
- * write no amax.  Per step: 3 aggregated steps, 3 face-ghost fills, 2 stage
- * combinations.  A time-step object may be used from one host thread at a
+ * write no amax.  Per step: 3 aggregated steps and 3 face-ghost fills, and
+ * for n = 12 and 16 2 stage combinations (for n = 8 they are part of the
+ * steps).  A time-step object may be used from one host thread at a
  * time; hydro_rk3_destroy waits for its work.
  * Errors: as hydro_step and hydro_ghost_fill; HYDRO_EINVAL for k outside
  * 1..3 or overlapping buffers.

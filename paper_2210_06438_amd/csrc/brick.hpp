@@ -118,8 +118,8 @@ __global__ void __launch_bounds__(256) ghost_fill_faces_kernel(double* __restric
 
 // out = a x + b y on the interior cells of every sub-grid, each product and
 // the sum rounded once (no contraction).  One work-group per (sub-grid,
-// field).  out may be x itself: each element is read and written by the
-// same lane.
+// field).  out may be x or y itself: each element is read and written by
+// the same lane.
 template <int N>
 __global__ void __launch_bounds__(256) rk_combine_kernel(double* out, const double* x,
                                                          const double* y, double a, double b,

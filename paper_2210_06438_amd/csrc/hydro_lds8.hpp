@@ -261,6 +261,17 @@ __device__ __forceinline__ void recon_at(Recon<K>& rc, const double (&q)[K],
   recon_step<(I < 6 ? I : 6), K>(rc, q, Wm, Wp);
 }
 
+// Optional blend of the step's result with another state, for the stages
+// of a multi-stage time-step: the stored value becomes a x + b U_out, each
+// product and the sum rounded once (no contraction), where x is the element
+// `delta` doubles from the output element (another brick buffer of the same
+// layout, or the output itself when delta = 0: each element is read and
+// written by the same lane).
+struct BlendArgs {
+  double a, b;
+  long delta;
+};
+
 // Finalize NFLD fields of a block from LDS, shared by all lanes of the
 // work-group (lane t takes the cells t, t + 192, ...): for every interior cell
 // the block owns, U_out = Z - lambda * (X + Y), where Z holds the z lanes'
@@ -270,12 +281,13 @@ __device__ __forceinline__ void recon_at(Recon<K>& rc, const double (&q)[K],
 // passive fields' separate x (acc region r) and y (held region r)
 // differences (SPLIT true; the same value, dF_x + dF_y).  With interior-only
 // outputs of an 8^3 sub-grid the lanes of a wave store 512 contiguous bytes.
-template <int NFLD, int MP, bool SPLIT>
+template <int NFLD, int MP, bool SPLIT, bool BLEND = false>
 __device__ __forceinline__ void finalize_shared(const double* __restrict__ held,
                                                 const double* __restrict__ acc, int kfirst,
                                                 double lambda, double* __restrict__ uout,
                                                 bool compact, long ofs, int ox, int oy, int oz,
-                                                int lox, int loy, int loz, int t) {
+                                                int lox, int loy, int loz, int t,
+                                                const BlendArgs& bl = BlendArgs{}) {
   constexpr int NI = MP - 2 * kGhost;
   constexpr int CELLS = NFLD * 512;
   constexpr int J = (CELLS + Lds8::kThreads - 1) / Lds8::kThreads;
@@ -295,6 +307,8 @@ __device__ __forceinline__ void finalize_shared(const double* __restrict__ held,
       if (x >= lox && y >= loy && z >= loz) {
         const long o = compact ? (kfirst + r) * ofs + ((long)(oz + z) * NI + oy + y) * NI + ox + x
                                : (kfirst + r) * Frame<MP>::FS + Frame<MP>::cell(x, y, z);
+        if constexpr (BLEND)
+          v = __dadd_rn(__dmul_rn(bl.a, as_global(uout)[o + bl.delta]), __dmul_rn(bl.b, v));
         __builtin_nontemporal_store(v, &as_global(uout)[o]);
       }
     }
@@ -313,10 +327,11 @@ __device__ __forceinline__ void finalize_shared(const double* __restrict__ held,
 // values for non-negative doubles; the slot is zeroed before the launch).
 // PARTS: the block stores its own maximum instead, at partial `part` of the
 // parent's slot (kAmaxParts per sub-grid), with a plain store.
-template <int F, int MP, bool MULTI, bool PARTS = false>
+template <int F, int MP, bool MULTI, bool PARTS = false, bool BLEND = false>
 __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int oy, int oz,
                                           int lox, int loy, int loz, double dt, double dx,
-                                          double* __restrict__ amax_out, int part = 0) {
+                                          double* __restrict__ amax_out, int part = 0,
+                                          const BlendArgs& bl = BlendArgs{}) {
   constexpr int M = Lds8::M;
   constexpr int N = Lds8::N;
   constexpr long FS = Frame<MP>::FS;
@@ -421,8 +436,8 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int
   load_share<NA, MP>(uin + 5 * FS, t, ps);
   load_ghosts<NA, MP>(uin + 5 * FS, gbase, gstride, pg);
   __syncthreads();   // hydro sums complete; tin free
-  finalize_shared<5, MP, false>(held, acc, 0, lambda, uout, compact, ofs, ox, oy, oz, lox, loy,
-                                loz, t);
+  finalize_shared<5, MP, false, BLEND>(held, acc, 0, lambda, uout, compact, ofs, ox, oy, oz,
+                                       lox, loy, loz, t, bl);
   store_share<NA>(tin, t, ps);
   __syncthreads();   // tin holds the first passive fields; the hydro core is written
   // second burst, in flight during the first marches
@@ -486,15 +501,15 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int
     if (p == NA - 1) {
       if constexpr (NB > 0) store_share<NB>(tin + NA * P, t, psb);
       __syncthreads();
-      finalize_shared<NA, MP, true>(held, acc, 5, lambda, uout, compact, ofs, ox, oy, oz, lox,
-                                    loy, loz, t);
+      finalize_shared<NA, MP, true, BLEND>(held, acc, 5, lambda, uout, compact, ofs, ox, oy, oz,
+                                           lox, loy, loz, t, bl);
       if constexpr (NB > 0) __syncthreads();   // group 1 read before group 2 writes
     }
     if constexpr (NB > 0) {
       if (p == NP - 1) {
         __syncthreads();
-        finalize_shared<NB, MP, true>(held, acc, 5 + NA, lambda, uout, compact, ofs, ox, oy, oz,
-                                      lox, loy, loz, t);
+        finalize_shared<NB, MP, true, BLEND>(held, acc, 5 + NA, lambda, uout, compact, ofs, ox,
+                                             oy, oz, lox, loy, loz, t, bl);
       }
     }
   }
@@ -567,6 +582,18 @@ __global__ void __launch_bounds__(Lds8::kThreads, 2)
   Blocks<MP>::geo(blockIdx.x % B, org, ox, oy, oz, lox, loy, loz);
   const DevDesc d = descs.d[blockIdx.x / B];
   lds8_step<F, MP, (B > 1)>(d, org, ox, oy, oz, lox, loy, loz, dt, dx, amax_out);
+}
+
+// 8^3 sub-grids whose stored results are blended (BlendArgs) with another
+// state: the stages of the device time-step.  No amax.
+template <int F>
+__global__ void __launch_bounds__(Lds8::kThreads, 2)
+    hydro_lds8_blend_kernel(const DevDesc* __restrict__ table, int count, double dt, double dx,
+                            BlendArgs bl) {
+  const int s = blockIdx.x;
+  if (s >= count) return;
+  const DevDesc d = table[s];
+  lds8_step<F, 14, false, false, true>(d, 0, 0, 0, 0, 0, 0, 0, dt, dx, nullptr, 0, bl);
 }
 
 // amax slots of a batch set to zero before a multi-block launch (a kernel,

@@ -13,6 +13,7 @@
 
 #include "../../include/hydroagg.h"
 #include "brick.hpp"
+#include "hydro_lds8.hpp"
 #include "internal.hpp"
 
 using hydro::api::fail;
@@ -132,7 +133,12 @@ struct hydro_rk3 {
   double* w = nullptr;
   double* s = nullptr;
   hydro_plan_t* step_uw = nullptr;  // E(u) -> w
+  // n = 8: the stage combinations fused into the step (blend kernel):
+  hydro::DevDesc* tab_ws = nullptr;  // descriptors of E(w) -> s
+  hydro::DevDesc* tab_su = nullptr;  // descriptors of E(s) -> u
+  // other edges: separate steps and combinations
   hydro_plan_t* step_ws = nullptr;  // E(w) -> s
+  hydro_plan_t* step_sw = nullptr;  // E(s) -> w
   hipStream_t capture = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -144,22 +150,51 @@ namespace {
 
 // Stage k of the Shu-Osher form with E(V) = V + dt L(V) (one hydro step):
 //   1: w = E(u)                    (u = U0; w = U1)
-//   2: s = E(w); w = 3/4 u + 1/4 s (w = U2)
-//   3: s = E(w); u = 1/3 u + 2/3 s (u = U3)
+//   2: s = 3/4 u + 1/4 E(w)        (s = U2)
+//   3: u = 1/3 u + 2/3 E(s)        (u = U3)
 // each followed by the face-ghost fill of the buffer just formed (the
-// face-centre step reads no edge or corner ghost).
+// face-centre step reads no edge or corner ghost).  For n = 8 the
+// combination is part of the step's stores (hydro_lds8_blend_kernel);
+// otherwise E goes to the free buffer and a combination kernel follows.
+template <int F>
+int launch_blend(const hydro::DevDesc* table, long count, double dt, double dx,
+                 const hydro::BlendArgs& bl, hipStream_t st) {
+  hipLaunchKernelGGL(hydro::hydro_lds8_blend_kernel<F>, dim3((unsigned)count),
+                     dim3(hydro::Lds8::kThreads), 0, st, table, (int)count, dt, dx, bl);
+  HIP_TRY(hipGetLastError());
+  return HYDRO_OK;
+}
+
+int blend_step(hydro_rk3* rk, const hydro::DevDesc* table, double dt, double dx,
+               const hydro::BlendArgs& bl, hipStream_t st) {
+  const long count = brick_count(rk->b);
+  return rk->b.nfields == 11 ? launch_blend<11>(table, count, dt, dx, bl, st)
+                             : launch_blend<6>(table, count, dt, dx, bl, st);
+}
+
 int stage(hydro_rk3* rk, int k, double dt, double dx, double* amax, hipStream_t st) {
   int rc;
   if (k == 1) {
     if ((rc = hydro::api::plan_enqueue(rk->step_uw, dt, dx, amax, st))) return rc;
     return launch_fill_faces(rk->b, rk->w, st);
   }
-  if ((rc = hydro::api::plan_enqueue(rk->step_ws, dt, dx, nullptr, st))) return rc;
   if (k == 2) {
-    if ((rc = launch_combine(rk->b, rk->w, rk->u, rk->s, 0.75, 0.25, st))) return rc;
-    return launch_fill_faces(rk->b, rk->w, st);
+    if (rk->tab_ws) {
+      const hydro::BlendArgs bl{0.75, 0.25, (long)(rk->u - rk->s)};
+      if ((rc = blend_step(rk, rk->tab_ws, dt, dx, bl, st))) return rc;
+    } else {
+      if ((rc = hydro::api::plan_enqueue(rk->step_ws, dt, dx, nullptr, st))) return rc;
+      if ((rc = launch_combine(rk->b, rk->s, rk->u, rk->s, 0.75, 0.25, st))) return rc;
+    }
+    return launch_fill_faces(rk->b, rk->s, st);
   }
-  if ((rc = launch_combine(rk->b, rk->u, rk->u, rk->s, 1.0 / 3.0, 2.0 / 3.0, st))) return rc;
+  if (rk->tab_su) {
+    const hydro::BlendArgs bl{1.0 / 3.0, 2.0 / 3.0, 0};
+    if ((rc = blend_step(rk, rk->tab_su, dt, dx, bl, st))) return rc;
+  } else {
+    if ((rc = hydro::api::plan_enqueue(rk->step_sw, dt, dx, nullptr, st))) return rc;
+    if ((rc = launch_combine(rk->b, rk->u, rk->u, rk->w, 1.0 / 3.0, 2.0 / 3.0, st))) return rc;
+  }
   return launch_fill_faces(rk->b, rk->u, st);
 }
 
@@ -176,6 +211,9 @@ void rk3_free(hydro_rk3* rk) {
   if (rk->capture) (void)hipStreamDestroy(rk->capture);
   if (rk->step_uw) (void)hydro_plan_destroy(rk->step_uw);
   if (rk->step_ws) (void)hydro_plan_destroy(rk->step_ws);
+  if (rk->step_sw) (void)hydro_plan_destroy(rk->step_sw);
+  if (rk->tab_ws) (void)hipFree(rk->tab_ws);
+  if (rk->tab_su) (void)hipFree(rk->tab_su);
   delete rk;
 }
 
@@ -217,24 +255,46 @@ int hydro_rk3_create(hydro_rk3_t** out, const hydro_brick_t* brick, double* u, d
   const long count = brick_count(*brick);
   const long M = brick->n + 2 * HYDRO_GHOST;
   const long stride = (long)brick->nfields * M * M * M;
-  std::vector<hydro_subgrid_t> a((size_t)count), c((size_t)count);
+  // the steps of the three stages: u -> w, w -> s, s -> (u or w)
+  std::vector<hydro_subgrid_t> a((size_t)count), c((size_t)count), e3((size_t)count);
   for (long i = 0; i < count; ++i) {
     a[i].u_in = u + i * stride;
     a[i].u_out = w + i * stride;
     c[i].u_in = w + i * stride;
     c[i].u_out = s + i * stride;
-    a[i].n = c[i].n = brick->n;
-    a[i].nfields = c[i].nfields = brick->nfields;
-    a[i].level = c[i].level = brick->level;
-    a[i].out_layout = c[i].out_layout = HYDRO_OUT_STORED;
+    e3[i].u_in = s + i * stride;
+    e3[i].u_out = (brick->n == 8 ? u : w) + i * stride;
+    a[i].n = c[i].n = e3[i].n = brick->n;
+    a[i].nfields = c[i].nfields = e3[i].nfields = brick->nfields;
+    a[i].level = c[i].level = e3[i].level = brick->level;
+    a[i].out_layout = c[i].out_layout = e3[i].out_layout = HYDRO_OUT_STORED;
   }
   hydro_rk3* rk = new hydro_rk3();
   rk->b = *brick;
   rk->u = u;
   rk->w = w;
   rk->s = s;
-  if ((rc = hydro_plan_create(&rk->step_uw, a.data(), (int32_t)count)) ||
-      (rc = hydro_plan_create(&rk->step_ws, c.data(), (int32_t)count))) {
+  if ((rc = hydro_plan_create(&rk->step_uw, a.data(), (int32_t)count))) {
+    rk3_free(rk);
+    return rc;
+  }
+  if (brick->n == 8) {
+    // device descriptor tables of the blended steps
+    std::vector<hydro::DevDesc> t2((size_t)count), t3((size_t)count);
+    for (long i = 0; i < count; ++i) {
+      t2[i] = hydro::api::device_desc(c[i], (int)i);
+      t3[i] = hydro::api::device_desc(e3[i], (int)i);
+    }
+    const size_t tb = sizeof(hydro::DevDesc) * (size_t)count;
+    if (hipMalloc((void**)&rk->tab_ws, tb) != hipSuccess ||
+        hipMalloc((void**)&rk->tab_su, tb) != hipSuccess ||
+        hipMemcpy(rk->tab_ws, t2.data(), tb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(rk->tab_su, t3.data(), tb, hipMemcpyHostToDevice) != hipSuccess) {
+      rk3_free(rk);
+      return fail(HYDRO_EHIP, "time-step descriptor tables");
+    }
+  } else if ((rc = hydro_plan_create(&rk->step_ws, c.data(), (int32_t)count)) ||
+             (rc = hydro_plan_create(&rk->step_sw, e3.data(), (int32_t)count))) {
     rk3_free(rk);
     return rc;
   }

@@ -103,6 +103,10 @@ CASES = {
     "random_11_fields_level_1": lambda: (
         ob.ghost_fill(workloads.random_smooth(6, n=8, nfields=11, seed=31), (3, 1, 2), (1, 0, 1)),
         (3, 1, 2), (1, 0, 1), 0.1, 1),
+    # 12^3 sub-grids: the steps and the stage combinations as separate kernels
+    "random_12_cubed": lambda: (
+        ob.ghost_fill(workloads.random_smooth(4, n=12, nfields=11, seed=32), (2, 2, 1), (0, 1, 0)),
+        (2, 2, 1), (0, 1, 0), 0.1, 0),
 }
 
 
@@ -125,10 +129,10 @@ def test_rk3_stages_match_the_oracle(dev, oracle_mod, case):
             print(f"rk3 {case}: stage {k}", flush=True)
             rk.stage(k, dt, dx, amax if k == 1 else None)
             torch.cuda.synchronize()
-            got = (w if k < 3 else u).cpu().numpy()
+            got = {1: w, 2: s, 3: u}[k].cpu().numpy()   # U1 in w, U2 in s, U3 in u
             # the stage fills face ghosts only (the only ghosts the next
-            # stage reads): compare interiors and face ghosts; w's edge and
-            # corner ghosts stay as they were (NaN)
+            # stage reads): compare interiors and face ghosts; the work
+            # buffers' edge and corner ghosts stay as they were (NaN)
             m = _face_mask(n)
             err = normwise_each(got[..., m], ref[k - 1][..., m])
             if k < 3:
