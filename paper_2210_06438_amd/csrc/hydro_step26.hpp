@@ -136,19 +136,50 @@ __device__ __forceinline__ double face26(const double* __restrict__ prim, gcptr 
   for (int f = 5; f < F; ++f) {
     const gcptr pf = u + f * S26::FS;
     double acc = 0.0;
+    if constexpr (F > 6) {
+      // the 10 line values of point p + 1 are loaded while point p is
+      // computed (compiled for a single passive field this form spilled
+      // over 700 bytes per lane, so the plain loop below serves that case)
+      double cur[10], nxt[10];
+      auto load = [&](int p, double (&v)[10]) {
+        int fc = face;   // opaque copy: offsets recomputed, not kept live
+        asm volatile("" : "+v"(fc));
+        int om[5], op[5];
+        face_lines<DIR>(fc, p % 3 - 1, p / 3 - 1, om, op);
 #pragma unroll
-    for (int p = 0; p < 9; ++p) {
-      const int s1 = p % 3 - 1, s2 = p / 3 - 1;
-      // an opaque copy of the face index: the line offsets are recomputed
-      // at every point (a few integer ops) instead of being kept live from
-      // the hydro points through every field, which would spill them
-      int fc = face;
-      asm volatile("" : "+v"(fc));
-      int om[5], op[5];
-      face_lines<DIR>(fc, s1, s2, om, op);
-      const double w = (s1 == 0 && s2 == 0) ? 16.0 : (s1 == 0 || s2 == 0) ? 4.0 : 1.0;
-      acc = acc + w * (wm[p] * point_passive(pf, om) + wp[p] * point_passive(pf, op));
-      __builtin_amdgcn_sched_barrier(0);
+        for (int k = 0; k < 5; ++k) {
+          v[k] = pf[om[k]];
+          v[5 + k] = pf[op[k]];
+        }
+      };
+      load(0, cur);
+#pragma unroll
+      for (int p = 0; p < 9; ++p) {
+        const int s1 = p % 3 - 1, s2 = p / 3 - 1;
+        if (p < 8) load(p + 1, nxt);
+        const double w = (s1 == 0 && s2 == 0) ? 16.0 : (s1 == 0 || s2 == 0) ? 4.0 : 1.0;
+        const double qm = ppm_right5(cur[0], cur[1], cur[2], cur[3], cur[4]);
+        const double qp = ppm_right5(cur[5], cur[6], cur[7], cur[8], cur[9]);
+        acc = acc + w * (wm[p] * qm + wp[p] * qp);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) cur[k] = nxt[k];
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < 9; ++p) {
+        const int s1 = p % 3 - 1, s2 = p / 3 - 1;
+        // an opaque copy of the face index: the line offsets are recomputed
+        // at every point (a few integer ops) instead of being kept live from
+        // the hydro points through every field, which would spill them
+        int fc = face;
+        asm volatile("" : "+v"(fc));
+        int om[5], op[5];
+        face_lines<DIR>(fc, s1, s2, om, op);
+        const double w = (s1 == 0 && s2 == 0) ? 16.0 : (s1 == 0 || s2 == 0) ? 4.0 : 1.0;
+        acc = acc + w * (wm[p] * point_passive(pf, om) + wp[p] * point_passive(pf, op));
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
     fh[face * F + f] = acc * (1.0 / 36.0);
   }
