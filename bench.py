@@ -212,8 +212,9 @@ def region_leg(args, torch, hydroagg, workloads, dev):
 def timestep_leg(args, torch, hydroagg, workloads, dev, stream):
     """The paper's time-step shape (Table II: 512 sub-grids of 8^3 tiling a
     64^3 domain; three solver iterations per step, Section VI-A): one SSP-RK3
-    time-step -- 3 aggregated steps, 3 ghost fills, 2 stage combinations --
-    as ONE hipGraph launch on the device-resident brick."""
+    time-step -- 3 aggregated stage kernels, each with its stage combination
+    and face-ghost writes in its stores -- as ONE hipGraph launch on the
+    device-resident brick."""
     per_axis, n, nf = 8, 8, args.nfields
     log(f"time-step: {per_axis ** 3} sub-grids of {n}^3, F={nf}, periodic brick")
     U = workloads.brick(seed=7, n=n, per_axis=per_axis, nfields=nf)
@@ -244,8 +245,8 @@ def timestep_leg(args, torch, hydroagg, workloads, dev, stream):
     log(f"time-step: {ms * 1e3:.1f} us per SSP-RK3 step ({cells / (ms * 1e-3) / 1e6:.1f} M cell-steps/s)")
     return {"workload": f"{count} sub-grids of {n}^3 (+3 ghost layers) tiling a periodic "
                         f"{per_axis * n}^3 domain, {nf} FP64 fields, random smooth state",
-            "what": "one SSP-RK3 time-step = 3 aggregated hydro steps + 3 ghost fills + 2 stage "
-                    "combinations, one hipGraph launch",
+            "what": "one SSP-RK3 time-step = 3 aggregated stage kernels (hydro step, stage "
+                    "combination and face-ghost writes in one launch each), one hipGraph launch",
             "ms_per_timestep": round(ms, 5), "timesteps": args.timestep_steps,
             "cell_steps_per_s": round(cells / (ms * 1e-3), 1),
             "cell_updates_per_s": round(3 * cells / (ms * 1e-3), 1),

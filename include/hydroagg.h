@@ -274,8 +274,11 @@ int hydro_ghost_fill_faces(const hydro_brick_t *brick, double *u, void *stream);
  *   U1 = E(U0),  U2 = 3/4 U0 + 1/4 E(U1),  U3 = 1/3 U0 + 2/3 E(U2),
  * each combination rounded as a x + b y with the two products and the sum
  * rounded once (for n = 8 formed in the step's own stores),
- * each stage's result with its face ghosts refilled (hydro_ghost_fill_faces:
- * the stage reads no edge or corner ghost) before the next stage reads it.
+ * each stage's result with its face ghosts refilled (the stage reads no edge
+ * or corner ghost) before the next stage reads it: for n = 8 the stage
+ * kernel writes every stored value near a face also into the face ghost it
+ * stands for (bitwise what hydro_ghost_fill_faces would write), for n = 12
+ * and 16 hydro_ghost_fill_faces follows the stage.
  * hydro_rk3_create binds the brick to three caller-owned device brick
  * buffers: u (the state, with face ghosts filled on entry; it holds U3,
  * face ghosts filled, after a step; its edge and corner ghosts are left as
@@ -293,9 +296,9 @@ int hydro_ghost_fill_faces(const hydro_brick_t *brick, double *u, void *stream);
  * of hydro_rk3_step).  dt >= 0 and dx > 0 as in hydro_step; amax_dev (device,
  * one double per sub-grid, or NULL) receives the amax of stage 1, i.e. of
  * the state the step starts from (hydro_step's definition); the later stages
- * write no amax.  Per step: 3 aggregated steps and 3 face-ghost fills, and
- * for n = 12 and 16 2 stage combinations (for n = 8 they are part of the
- * steps).  A time-step object may be used from one host thread at a
+ * write no amax.  Per step: for n = 8, 3 stage kernels; for n = 12 and 16,
+ * 3 aggregated steps, 2 stage combinations and 3 face-ghost fills.  A
+ * time-step object may be used from one host thread at a
  * time; hydro_rk3_destroy waits for its work.
  * Errors: as hydro_step and hydro_ghost_fill; HYDRO_EINVAL for k outside
  * 1..3 or overlapping buffers.

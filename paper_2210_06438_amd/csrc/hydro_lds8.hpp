@@ -272,6 +272,59 @@ struct BlendArgs {
   long delta;
 };
 
+// Optional face-ghost writes of the stages of a time-step on a brick of
+// sub-grids (the ghost exchange of Section V-A done by the producer): every
+// stored interior value within kGhost cells of a face is also a face-ghost
+// value of the sub-grid across that face, and is written there too (periodic
+// axes wrap around the brick).  Under outflow at the domain's edge the cell
+// next to the edge fills this sub-grid's own kGhost layers there (the ghost
+// takes the nearest domain cell).  Sub-grid s of the brick sits at
+// (s % nb[0], s / nb[0] % nb[1], s / (nb[0] nb[1])), its stored block at
+// base + s sg_stride.  Edge and corner ghosts are not written: the
+// face-centre step reads none.  Within one launch every destination is a
+// ghost cell of the output buffer, which the launch does not read.
+struct FacePush {
+  double* base;
+  long sg_stride;
+  int nb[3];
+  int bc[3];   // 0 periodic, 1 outflow
+};
+
+template <int MP>
+__device__ __forceinline__ void push_faces(const FacePush& fp, int sg, int f, int x, int y,
+                                           int z, double v) {
+  constexpr int N = MP - 2 * kGhost;
+  const int c[3] = {x, y, z};
+  const int bs[3] = {sg % fp.nb[0], (sg / fp.nb[0]) % fp.nb[1], sg / (fp.nb[0] * fp.nb[1])};
+  const long sgs[3] = {1, fp.nb[0], (long)fp.nb[0] * fp.nb[1]};   // sub-grids per step
+  const long st[3] = {1, MP, (long)MP * MP};                      // stored cells per step
+  double* const own = fp.base + sg * fp.sg_stride + f * Frame<MP>::FS + Frame<MP>::cell(x, y, z);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const bool lo = bs[a] == 0, hi = bs[a] == fp.nb[a] - 1, outflow = fp.bc[a] != 0;
+    if (c[a] < kGhost) {
+      if (!(outflow && lo)) {
+        // the lower neighbour's ghost at stored coordinate c + N + kGhost
+        const long nsg = lo ? (fp.nb[a] - 1) * sgs[a] : -sgs[a];
+        as_global(own)[nsg * fp.sg_stride + N * st[a]] = v;
+      } else if (c[a] == 0) {
+#pragma unroll
+        for (int k = 1; k <= kGhost; ++k) as_global(own)[-k * st[a]] = v;
+      }
+    }
+    if (c[a] >= N - kGhost) {
+      if (!(outflow && hi)) {
+        // the upper neighbour's ghost at stored coordinate c - N + kGhost
+        const long nsg = hi ? -(fp.nb[a] - 1) * sgs[a] : sgs[a];
+        as_global(own)[nsg * fp.sg_stride - N * st[a]] = v;
+      } else if (c[a] == N - 1) {
+#pragma unroll
+        for (int k = 1; k <= kGhost; ++k) as_global(own)[k * st[a]] = v;
+      }
+    }
+  }
+}
+
 // Finalize NFLD fields of a block from LDS, shared by all lanes of the
 // work-group (lane t takes the cells t, t + 192, ...): for every interior cell
 // the block owns, U_out = Z - lambda * (X + Y), where Z holds the z lanes'
@@ -281,13 +334,14 @@ struct BlendArgs {
 // passive fields' separate x (acc region r) and y (held region r)
 // differences (SPLIT true; the same value, dF_x + dF_y).  With interior-only
 // outputs of an 8^3 sub-grid the lanes of a wave store 512 contiguous bytes.
-template <int NFLD, int MP, bool SPLIT, bool BLEND = false>
+template <int NFLD, int MP, bool SPLIT, bool BLEND = false, bool PUSH = false>
 __device__ __forceinline__ void finalize_shared(const double* __restrict__ held,
                                                 const double* __restrict__ acc, int kfirst,
                                                 double lambda, double* __restrict__ uout,
                                                 bool compact, long ofs, int ox, int oy, int oz,
                                                 int lox, int loy, int loz, int t,
-                                                const BlendArgs& bl = BlendArgs{}) {
+                                                const BlendArgs& bl = BlendArgs{},
+                                                const FacePush& fp = FacePush{}, int sg = 0) {
   constexpr int NI = MP - 2 * kGhost;
   constexpr int CELLS = NFLD * 512;
   constexpr int J = (CELLS + Lds8::kThreads - 1) / Lds8::kThreads;
@@ -310,6 +364,7 @@ __device__ __forceinline__ void finalize_shared(const double* __restrict__ held,
         if constexpr (BLEND)
           v = __dadd_rn(__dmul_rn(bl.a, as_global(uout)[o + bl.delta]), __dmul_rn(bl.b, v));
         __builtin_nontemporal_store(v, &as_global(uout)[o]);
+        if constexpr (PUSH) push_faces<MP>(fp, sg, kfirst + r, x, y, z, v);
       }
     }
   }
@@ -327,11 +382,12 @@ __device__ __forceinline__ void finalize_shared(const double* __restrict__ held,
 // values for non-negative doubles; the slot is zeroed before the launch).
 // PARTS: the block stores its own maximum instead, at partial `part` of the
 // parent's slot (kAmaxParts per sub-grid), with a plain store.
-template <int F, int MP, bool MULTI, bool PARTS = false, bool BLEND = false>
+template <int F, int MP, bool MULTI, bool PARTS = false, bool BLEND = false, bool PUSH = false>
 __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int oy, int oz,
                                           int lox, int loy, int loz, double dt, double dx,
                                           double* __restrict__ amax_out, int part = 0,
-                                          const BlendArgs& bl = BlendArgs{}) {
+                                          const BlendArgs& bl = BlendArgs{},
+                                          const FacePush& fp = FacePush{}) {
   constexpr int M = Lds8::M;
   constexpr int N = Lds8::N;
   constexpr long FS = Frame<MP>::FS;
@@ -436,8 +492,8 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int
   load_share<NA, MP>(uin + 5 * FS, t, ps);
   load_ghosts<NA, MP>(uin + 5 * FS, gbase, gstride, pg);
   __syncthreads();   // hydro sums complete; tin free
-  finalize_shared<5, MP, false, BLEND>(held, acc, 0, lambda, uout, compact, ofs, ox, oy, oz,
-                                       lox, loy, loz, t, bl);
+  finalize_shared<5, MP, false, BLEND, PUSH>(held, acc, 0, lambda, uout, compact, ofs, ox, oy,
+                                             oz, lox, loy, loz, t, bl, fp, d.index);
   store_share<NA>(tin, t, ps);
   __syncthreads();   // tin holds the first passive fields; the hydro core is written
   // second burst, in flight during the first marches
@@ -501,15 +557,16 @@ __device__ __forceinline__ void lds8_step(const DevDesc& d, int org, int ox, int
     if (p == NA - 1) {
       if constexpr (NB > 0) store_share<NB>(tin + NA * P, t, psb);
       __syncthreads();
-      finalize_shared<NA, MP, true, BLEND>(held, acc, 5, lambda, uout, compact, ofs, ox, oy, oz,
-                                           lox, loy, loz, t, bl);
+      finalize_shared<NA, MP, true, BLEND, PUSH>(held, acc, 5, lambda, uout, compact, ofs, ox,
+                                                 oy, oz, lox, loy, loz, t, bl, fp, d.index);
       if constexpr (NB > 0) __syncthreads();   // group 1 read before group 2 writes
     }
     if constexpr (NB > 0) {
       if (p == NP - 1) {
         __syncthreads();
-        finalize_shared<NB, MP, true, BLEND>(held, acc, 5 + NA, lambda, uout, compact, ofs, ox,
-                                             oy, oz, lox, loy, loz, t, bl);
+        finalize_shared<NB, MP, true, BLEND, PUSH>(held, acc, 5 + NA, lambda, uout, compact,
+                                                   ofs, ox, oy, oz, lox, loy, loz, t, bl, fp,
+                                                   d.index);
       }
     }
   }
@@ -584,16 +641,25 @@ __global__ void __launch_bounds__(Lds8::kThreads, 2)
   lds8_step<F, MP, (B > 1)>(d, org, ox, oy, oz, lox, loy, loz, dt, dx, amax_out);
 }
 
-// 8^3 sub-grids whose stored results are blended (BlendArgs) with another
-// state: the stages of the device time-step.  No amax.
-template <int F>
+// The stages of the device time-step on a brick of 8^3 sub-grids (stored
+// layout, descriptor index = brick index): the step's stores, blended with
+// another state when BLEND (BlendArgs), each also written to the face ghosts
+// it stands for (FacePush).  amax as the table kernel, when amax_out is set.
+// When count is a multiple of 8, XCD k (work-groups w = k mod 8) takes the
+// k-th eighth of the brick, a run of consecutive sub-grids in brick order
+// (x fastest; a whole z layer of an 8 x 8 x 8 brick): a sub-grid and its x
+// neighbours then mostly share one L2, where the 24-byte ghost rows one
+// writes and the interior rows the other writes meet in the same lines.
+template <int F, bool BLEND>
 __global__ void __launch_bounds__(Lds8::kThreads, 2)
-    hydro_lds8_blend_kernel(const DevDesc* __restrict__ table, int count, double dt, double dx,
-                            BlendArgs bl) {
-  const int s = blockIdx.x;
+    hydro_lds8_stage_kernel(const DevDesc* __restrict__ table, int count, double dt, double dx,
+                            BlendArgs bl, FacePush fp, double* __restrict__ amax_out) {
+  const int w = blockIdx.x;
+  const int s = (count & 7) ? w : (w & 7) * (count >> 3) + (w >> 3);
   if (s >= count) return;
   const DevDesc d = table[s];
-  lds8_step<F, 14, false, false, true>(d, 0, 0, 0, 0, 0, 0, 0, dt, dx, nullptr, 0, bl);
+  lds8_step<F, 14, false, false, BLEND, true>(d, 0, 0, 0, 0, 0, 0, 0, dt, dx, amax_out, 0, bl,
+                                              fp);
 }
 
 // amax slots of a batch set to zero before a multi-block launch (a kernel,

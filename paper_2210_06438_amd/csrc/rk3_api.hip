@@ -132,11 +132,13 @@ struct hydro_rk3 {
   double* u = nullptr;
   double* w = nullptr;
   double* s = nullptr;
-  hydro_plan_t* step_uw = nullptr;  // E(u) -> w
-  // n = 8: the stage combinations fused into the step (blend kernel):
+  // n = 8: stage kernels with the combinations and the face-ghost writes in
+  // their stores (hydro_lds8_stage_kernel):
+  hydro::DevDesc* tab_uw = nullptr;  // descriptors of E(u) -> w
   hydro::DevDesc* tab_ws = nullptr;  // descriptors of E(w) -> s
   hydro::DevDesc* tab_su = nullptr;  // descriptors of E(s) -> u
-  // other edges: separate steps and combinations
+  // other edges: separate steps, combinations and face-ghost fills
+  hydro_plan_t* step_uw = nullptr;  // E(u) -> w
   hydro_plan_t* step_ws = nullptr;  // E(w) -> s
   hydro_plan_t* step_sw = nullptr;  // E(s) -> w
   hipStream_t capture = nullptr;
@@ -152,49 +154,65 @@ namespace {
 //   1: w = E(u)                    (u = U0; w = U1)
 //   2: s = 3/4 u + 1/4 E(w)        (s = U2)
 //   3: u = 1/3 u + 2/3 E(s)        (u = U3)
-// each followed by the face-ghost fill of the buffer just formed (the
-// face-centre step reads no edge or corner ghost).  For n = 8 the
-// combination is part of the step's stores (hydro_lds8_blend_kernel);
-// otherwise E goes to the free buffer and a combination kernel follows.
+// each leaving the face ghosts of the buffer it forms filled (the
+// face-centre step reads no edge or corner ghost).  For n = 8 one stage
+// kernel does all of it: the combination and the face-ghost writes are part
+// of the step's stores.  Otherwise E goes to the free buffer, and a
+// combination kernel and the face-ghost fill follow.
 template <int F>
-int launch_blend(const hydro::DevDesc* table, long count, double dt, double dx,
-                 const hydro::BlendArgs& bl, hipStream_t st) {
-  hipLaunchKernelGGL(hydro::hydro_lds8_blend_kernel<F>, dim3((unsigned)count),
-                     dim3(hydro::Lds8::kThreads), 0, st, table, (int)count, dt, dx, bl);
+int launch_stage(const hydro::DevDesc* table, long count, double dt, double dx, bool blend,
+                 const hydro::BlendArgs& bl, const hydro::FacePush& fp, double* amax,
+                 hipStream_t st) {
+  const dim3 grid((unsigned)count), block(hydro::Lds8::kThreads);
+  if (!blend)
+    hipLaunchKernelGGL((hydro::hydro_lds8_stage_kernel<F, false>), grid, block, 0, st, table,
+                       (int)count, dt, dx, bl, fp, amax);
+  else
+    hipLaunchKernelGGL((hydro::hydro_lds8_stage_kernel<F, true>), grid, block, 0, st, table,
+                       (int)count, dt, dx, bl, fp, amax);
   HIP_TRY(hipGetLastError());
   return HYDRO_OK;
 }
 
-int blend_step(hydro_rk3* rk, const hydro::DevDesc* table, double dt, double dx,
-               const hydro::BlendArgs& bl, hipStream_t st) {
+// bl = nullptr: the plain step (stage 1)
+int stage8(hydro_rk3* rk, const hydro::DevDesc* table, double* out, const hydro::BlendArgs* bl,
+           double dt, double dx, double* amax, hipStream_t st) {
   const long count = brick_count(rk->b);
-  return rk->b.nfields == 11 ? launch_blend<11>(table, count, dt, dx, bl, st)
-                             : launch_blend<6>(table, count, dt, dx, bl, st);
+  const hydro::BrickGeo g = geo_of(rk->b);
+  hydro::FacePush fp;
+  fp.base = out;
+  fp.sg_stride = g.sg_stride;
+  for (int d = 0; d < 3; ++d) {
+    fp.nb[d] = g.nb[d];
+    fp.bc[d] = g.bc[d];
+  }
+  const hydro::BlendArgs b = bl ? *bl : hydro::BlendArgs{0.0, 1.0, 0};
+  return rk->b.nfields == 11 ? launch_stage<11>(table, count, dt, dx, bl != nullptr, b, fp, amax, st)
+                             : launch_stage<6>(table, count, dt, dx, bl != nullptr, b, fp, amax, st);
 }
 
 int stage(hydro_rk3* rk, int k, double dt, double dx, double* amax, hipStream_t st) {
   int rc;
+  if (rk->tab_uw) {
+    if (k == 1) return stage8(rk, rk->tab_uw, rk->w, nullptr, dt, dx, amax, st);
+    if (k == 2) {
+      const hydro::BlendArgs bl{0.75, 0.25, (long)(rk->u - rk->s)};
+      return stage8(rk, rk->tab_ws, rk->s, &bl, dt, dx, nullptr, st);
+    }
+    const hydro::BlendArgs bl{1.0 / 3.0, 2.0 / 3.0, 0};
+    return stage8(rk, rk->tab_su, rk->u, &bl, dt, dx, nullptr, st);
+  }
   if (k == 1) {
     if ((rc = hydro::api::plan_enqueue(rk->step_uw, dt, dx, amax, st))) return rc;
     return launch_fill_faces(rk->b, rk->w, st);
   }
   if (k == 2) {
-    if (rk->tab_ws) {
-      const hydro::BlendArgs bl{0.75, 0.25, (long)(rk->u - rk->s)};
-      if ((rc = blend_step(rk, rk->tab_ws, dt, dx, bl, st))) return rc;
-    } else {
-      if ((rc = hydro::api::plan_enqueue(rk->step_ws, dt, dx, nullptr, st))) return rc;
-      if ((rc = launch_combine(rk->b, rk->s, rk->u, rk->s, 0.75, 0.25, st))) return rc;
-    }
+    if ((rc = hydro::api::plan_enqueue(rk->step_ws, dt, dx, nullptr, st))) return rc;
+    if ((rc = launch_combine(rk->b, rk->s, rk->u, rk->s, 0.75, 0.25, st))) return rc;
     return launch_fill_faces(rk->b, rk->s, st);
   }
-  if (rk->tab_su) {
-    const hydro::BlendArgs bl{1.0 / 3.0, 2.0 / 3.0, 0};
-    if ((rc = blend_step(rk, rk->tab_su, dt, dx, bl, st))) return rc;
-  } else {
-    if ((rc = hydro::api::plan_enqueue(rk->step_sw, dt, dx, nullptr, st))) return rc;
-    if ((rc = launch_combine(rk->b, rk->u, rk->u, rk->w, 1.0 / 3.0, 2.0 / 3.0, st))) return rc;
-  }
+  if ((rc = hydro::api::plan_enqueue(rk->step_sw, dt, dx, nullptr, st))) return rc;
+  if ((rc = launch_combine(rk->b, rk->u, rk->u, rk->w, 1.0 / 3.0, 2.0 / 3.0, st))) return rc;
   return launch_fill_faces(rk->b, rk->u, st);
 }
 
@@ -212,6 +230,7 @@ void rk3_free(hydro_rk3* rk) {
   if (rk->step_uw) (void)hydro_plan_destroy(rk->step_uw);
   if (rk->step_ws) (void)hydro_plan_destroy(rk->step_ws);
   if (rk->step_sw) (void)hydro_plan_destroy(rk->step_sw);
+  if (rk->tab_uw) (void)hipFree(rk->tab_uw);
   if (rk->tab_ws) (void)hipFree(rk->tab_ws);
   if (rk->tab_su) (void)hipFree(rk->tab_su);
   delete rk;
@@ -274,26 +293,26 @@ int hydro_rk3_create(hydro_rk3_t** out, const hydro_brick_t* brick, double* u, d
   rk->u = u;
   rk->w = w;
   rk->s = s;
-  if ((rc = hydro_plan_create(&rk->step_uw, a.data(), (int32_t)count))) {
-    rk3_free(rk);
-    return rc;
-  }
   if (brick->n == 8) {
-    // device descriptor tables of the blended steps
-    std::vector<hydro::DevDesc> t2((size_t)count), t3((size_t)count);
+    // device descriptor tables of the three stage kernels (index = brick index)
+    std::vector<hydro::DevDesc> t1((size_t)count), t2((size_t)count), t3((size_t)count);
     for (long i = 0; i < count; ++i) {
+      t1[i] = hydro::api::device_desc(a[i], (int)i);
       t2[i] = hydro::api::device_desc(c[i], (int)i);
       t3[i] = hydro::api::device_desc(e3[i], (int)i);
     }
     const size_t tb = sizeof(hydro::DevDesc) * (size_t)count;
-    if (hipMalloc((void**)&rk->tab_ws, tb) != hipSuccess ||
+    if (hipMalloc((void**)&rk->tab_uw, tb) != hipSuccess ||
+        hipMalloc((void**)&rk->tab_ws, tb) != hipSuccess ||
         hipMalloc((void**)&rk->tab_su, tb) != hipSuccess ||
+        hipMemcpy(rk->tab_uw, t1.data(), tb, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(rk->tab_ws, t2.data(), tb, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(rk->tab_su, t3.data(), tb, hipMemcpyHostToDevice) != hipSuccess) {
       rk3_free(rk);
       return fail(HYDRO_EHIP, "time-step descriptor tables");
     }
-  } else if ((rc = hydro_plan_create(&rk->step_ws, c.data(), (int32_t)count)) ||
+  } else if ((rc = hydro_plan_create(&rk->step_uw, a.data(), (int32_t)count)) ||
+             (rc = hydro_plan_create(&rk->step_ws, c.data(), (int32_t)count)) ||
              (rc = hydro_plan_create(&rk->step_sw, e3.data(), (int32_t)count))) {
     rk3_free(rk);
     return rc;

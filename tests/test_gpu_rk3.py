@@ -1,8 +1,10 @@
 """The device time-step on a brick: ghost fill, full and face ghosts only
 (bitwise, against the brick oracle), and the three SSP-RK3 stages (per
 stage, against the oracle's composition of its own hydro stage, on the
-interiors and face ghosts the time-step fills), the graph form (bitwise the
-launches), and Sod's shock tube converging on the GPU."""
+interiors and face ghosts the time-step fills: for 8^3 sub-grids the stage
+kernels write the face ghosts from their own stores, other edges run the
+fill kernel), the graph form (bitwise the launches), and Sod's shock tube
+converging on the GPU."""
 import numpy as np
 import pytest
 
@@ -103,6 +105,11 @@ CASES = {
     "random_11_fields_level_1": lambda: (
         ob.ghost_fill(workloads.random_smooth(6, n=8, nfields=11, seed=31), (3, 1, 2), (1, 0, 1)),
         (3, 1, 2), (1, 0, 1), 0.1, 1),
+    # one sub-grid across the outflow axes: both edges of x and z are the
+    # domain's, so every face ghost there comes from the sub-grid itself
+    "outflow_single_layers": lambda: (
+        ob.ghost_fill(workloads.random_smooth(2, n=8, nfields=6, seed=33), (1, 2, 1), (1, 0, 1)),
+        (1, 2, 1), (1, 0, 1), 0.1, 0),
     # 12^3 sub-grids: the steps and the stage combinations as separate kernels
     "random_12_cubed": lambda: (
         ob.ghost_fill(workloads.random_smooth(4, n=12, nfields=11, seed=32), (2, 2, 1), (0, 1, 0)),
