@@ -130,13 +130,21 @@ def test_rk3_stages_match_the_oracle(dev, oracle_mod, case):
     w = torch.full_like(u, float("nan"))
     s = torch.full_like(u, float("nan"))
     amax = torch.zeros(count, dtype=torch.float64, device=dev)
-    rk = hydroagg.RK3(hydroagg.brick(n, nf, nb, bc, level), u, w, s)
+    b = hydroagg.brick(n, nf, nb, bc, level)
+    rk = hydroagg.RK3(b, u, w, s)
     try:
         for k in (1, 2, 3):
             print(f"rk3 {case}: stage {k}", flush=True)
             rk.stage(k, dt, dx, amax if k == 1 else None)
             torch.cuda.synchronize()
-            got = {1: w, 2: s, 3: u}[k].cpu().numpy()   # U1 in w, U2 in s, U3 in u
+            out = {1: w, 2: s, 3: u}[k]                   # U1 in w, U2 in s, U3 in u
+            got = out.cpu().numpy()
+            # the face ghosts the stage left are bitwise what the fill kernel
+            # copies from the interiors it formed
+            refill = out.clone()
+            hydroagg.ghost_fill_faces(b, refill)
+            torch.cuda.synchronize()
+            assert np.array_equal(refill.cpu().numpy(), got, equal_nan=True), k
             # the stage fills face ghosts only (the only ghosts the next
             # stage reads): compare interiors and face ghosts; the work
             # buffers' edge and corner ghosts stay as they were (NaN)
