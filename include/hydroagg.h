@@ -435,7 +435,8 @@ const void *hydro_region_kernel(int32_t which);
  *     non-aggregated baseline; r is not used and may be NULL).
  * Every sub-grid is stepped exactly as hydro_step steps it (bitwise).
  * amax_host (host, count doubles, or NULL) receives each task's amax;
- * *seconds the wall time from the first thread's start to the last join.
+ * *seconds the wall time from the moment every thread has made its set-up
+ * (EACH: its stream and buffers) to the last join.
  * Errors: HYDRO_EINVAL for bad arguments; the first failing task's error
  * otherwise (the other threads then stop taking tasks).  Allocates (threads,
  * per-thread streams): set-up and measurement, not a step path.

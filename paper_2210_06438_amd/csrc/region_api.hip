@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <string>
+#include <system_error>
 
 #include <atomic>
 #include <chrono>
@@ -328,6 +329,9 @@ int hydro_region_drive(hydro_region_t* r, const hydro_subgrid_t* sg, int32_t cou
   const void* kernel = hydro_region_kernel(nf == 11 ? HYDRO_REGION_STEP8_F11 : HYDRO_REGION_STEP8_F6);
   std::atomic<int32_t> next{0};
   std::atomic<int> first_rc{HYDRO_OK};
+  // the clock starts once every worker has made its per-thread set-up
+  std::atomic<int> ready{0};
+  std::atomic<bool> go{false};
   std::vector<std::string> errs((size_t)n_threads);
   auto worker = [&](int w) {
     hipStream_t st = nullptr;
@@ -342,6 +346,8 @@ int hydro_region_drive(hydro_region_t* r, const hydro_subgrid_t* sg, int32_t cou
         errs[w] = "per-thread stream or buffers";
       }
     }
+    ready.fetch_add(1);
+    while (!go.load()) std::this_thread::yield();
     while (first_rc.load() == HYDRO_OK) {
       const int32_t i = next.fetch_add(1);
       if (i >= count) break;
@@ -367,13 +373,24 @@ int hydro_region_drive(hydro_region_t* r, const hydro_subgrid_t* sg, int32_t cou
     if (dev_amax) (void)hipFree(dev_amax);
     if (st) (void)hipStreamDestroy(st);
   };
-  const auto t0 = std::chrono::steady_clock::now();
   std::vector<std::thread> ts;
-  for (int w = 0; w < n_threads; ++w) ts.emplace_back(worker, w);
+  std::string start_err;
+  try {
+    for (int w = 0; w < n_threads; ++w) ts.emplace_back(worker, w);
+  } catch (const std::system_error&) {
+    // fewer threads than asked for: the ones started end without tasks
+    int z = HYDRO_OK;
+    first_rc.compare_exchange_strong(z, HYDRO_EINVAL);
+    start_err = "could not start the worker threads";
+  }
+  while (ready.load() < (int)ts.size()) std::this_thread::yield();
+  const auto t0 = std::chrono::steady_clock::now();
+  go.store(true);
   for (auto& th : ts) th.join();
   *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   const int rc = first_rc.load();
   if (rc) {
+    if (!start_err.empty()) return fail(rc, "%s", start_err.c_str());
     for (auto& e : errs)
       if (!e.empty()) return fail(rc, "%s", e.c_str());
     return fail(rc, "a task failed");
