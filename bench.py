@@ -141,6 +141,19 @@ def uneven_leg(args, torch, hydroagg, workloads, dev, stream):
     # one hipGraph launch, and as eager launches beside it
     ms = back_to_back(lambda: plan.graph(dt, dx, amax, stream), args.uneven_steps)
     eager_ms = back_to_back(lambda: plan.step(dt, dx, amax, stream), args.uneven_steps)
+    # each edge class alone: its own plan, eager launches (the class's kernel)
+    per_class = {}
+    if not args.no_uneven_classes:
+        for (N, _, t_in, _), d in zip(tensors, descs):
+            cplan = hydroagg.Plan(d)
+            camax = torch.zeros(d[1], dtype=torch.float64, device=dev)
+            cms = back_to_back(lambda: cplan.step(dt, dx, camax, stream), args.uneven_steps)
+            cplan.close()
+            ccells = int(t_in.shape[0]) * N ** 3
+            per_class[int(N)] = {"subgrids": int(t_in.shape[0]), "us_per_step": round(cms * 1e3, 2),
+                                 "value": round(ccells / (cms * 1e-3), 1)}
+            log(f"uneven: class {N}^3 alone ({t_in.shape[0]} sub-grids): {cms * 1e3:.1f} us/step, "
+                f"{ccells / cms / 1e6:.3f} G cell-updates/s")
     each_ms = None
     if args.uneven_each:
         e0.record(stream)
@@ -165,6 +178,7 @@ def uneven_leg(args, torch, hydroagg, workloads, dev, stream):
         "per_subgrid_launch": None if each_ms is None else {
             "ms_per_step": round(each_ms, 3), "value": round(cells / (each_ms * 1e-3), 1)},
         "aggregation_speedup": None if each_ms is None else round(each_ms / ms, 2),
+        "per_class_alone": per_class or None,
     }
     return res, tensors, dt, dx, groups
 
@@ -612,6 +626,8 @@ def main():
                     help="timed repetitions of a plain device copy of the input buffer")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-size leg")
+    ap.add_argument("--no-uneven-classes", action="store_true",
+                    help="skip timing each edge class of the uneven leg alone")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--uneven-count", type=int, default=3000)
     ap.add_argument("--uneven-steps", type=int, default=100)
