@@ -625,6 +625,8 @@ def main():
     ap.add_argument("--copy-reps", type=int, default=10,
                     help="timed repetitions of a plain device copy of the input buffer")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--launch-samples", type=int, default=60,
+                    help="headline launches timed one by one for the per-launch median")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-size leg")
     ap.add_argument("--no-uneven-classes", action="store_true",
                     help="skip timing each edge class of the uneven leg alone")
@@ -637,7 +639,7 @@ def main():
     ap.add_argument("--per-task-max-rate", type=float, default=200000.0,
                     help="skip the per-task-launch baseline above this rate (it saturates "
                          "near 60k tasks/s)")
-    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-width", type=int, default=64)
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--serve-budget-mb", type=float, default=64.0)
@@ -753,6 +755,24 @@ def main():
     # kernel's average launch duration (plus the small dispatch gap between
     # back-to-back launches): the roofline's denominator.
     kernel_ms = ms
+
+    # ---- per-launch durations: the same step, each launch between its own
+    # event pair (reported beside the value, which stays the timed region's
+    # mean)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.launch_samples)]
+    for a_, b_ in evs:
+        a_.record(stream)
+        plan.step(dt, dx, amax, stream)
+        b_.record(stream)
+    torch.cuda.synchronize()
+    lat = sorted(1e3 * a_.elapsed_time(b_) for a_, b_ in evs)
+    launch_durations = None if not lat else {
+        "launches": len(lat), "median_us": round(statistics.median(lat), 2),
+        "min_us": round(lat[0], 2), "max_us": round(lat[-1], 2)}
+    if lat:
+        log(f"per-launch durations: median {launch_durations['median_us']} us over {len(lat)} "
+            f"launches (min {launch_durations['min_us']}, max {launch_durations['max_us']})")
 
     # ---- the same batch replayed as one hipGraph launch per step -----------
     for _ in range(3):
@@ -906,6 +926,7 @@ def main():
             "value": round(cells / (each_ms * 1e-3), 1), "ms_per_step": round(each_ms, 4),
             "launches_per_step": count},
         "aggregation_speedup": None if each_ms is None else round(each_ms / ms, 2),
+        "launch_durations": launch_durations,
         "graph_replay": {"ms_per_step": round(graph_ms, 5),
                          "value": round(cells / (graph_ms * 1e-3), 1),
                          "note": "the same step captured once and replayed as one hipGraph "
