@@ -194,6 +194,8 @@ __device__ __forceinline__ void q4_step(const DevDesc& d, int group, double dt, 
                             : org + Frame<MP>::line(2, a, b, kGhost);
 
   // ---- stage the hydro core ---------------------------------------------
+  // loads issued at a raised wave priority, as in the 8^3 tile
+  __builtin_amdgcn_s_setprio(2);
   {
     Share4<5> sh;
     q4_load_share<5, MP>(uin, group, t, sh);
@@ -202,6 +204,7 @@ __device__ __forceinline__ void q4_step(const DevDesc& d, int group, double dt, 
   }
   double g[5][6];
   q4_load_ghosts<5, MP>(uin, gbase, gstride, g);
+  __builtin_amdgcn_s_setprio(0);
   __syncthreads();
 
   double smax = 0.0;
