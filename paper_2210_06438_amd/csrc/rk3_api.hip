@@ -196,7 +196,10 @@ int stage(hydro_rk3* rk, int k, double dt, double dx, double* amax, hipStream_t 
   if (rk->tab_uw) {
     if (k == 1) return stage8(rk, rk->tab_uw, rk->w, nullptr, dt, dx, amax, st);
     if (k == 2) {
-      const hydro::BlendArgs bl{0.75, 0.25, (long)(rk->u - rk->s)};
+      // u's element from s's, in doubles (addresses compared as integers:
+      // the buffers are separate allocations, both 16-byte aligned)
+      const long delta = ((long)(intptr_t)rk->u - (long)(intptr_t)rk->s) / (long)sizeof(double);
+      const hydro::BlendArgs bl{0.75, 0.25, delta};
       return stage8(rk, rk->tab_ws, rk->s, &bl, dt, dx, nullptr, st);
     }
     const hydro::BlendArgs bl{1.0 / 3.0, 2.0 / 3.0, 0};
