@@ -98,6 +98,40 @@ __device__ __forceinline__ void face_lines(int face, int s1, int s2, int (&om)[5
   line5(lo[0] + (DIR == 0), lo[1] + (DIR == 1), lo[2] + (DIR == 2), ep[0], ep[1], ep[2], op);
 }
 
+// The central-upwind flux of core_flux for a face normal to axis DIR known
+// at compile time: the normal velocity is that component itself and the
+// pressure enters that momentum flux alone, so the products with the zero
+// components of the unit normal are not formed (the values are the same up
+// to the sign of a zero).
+template <int DIR>
+__device__ __forceinline__ double core_flux_axis(const double (&Wm)[5], const double (&Wp)[5],
+                                                 double (&Fh)[5], double& wm, double& wp) {
+  const double vnm = Wm[1 + DIR], vnp = Wp[1 + DIR];
+  const double gm = kGamma * Wm[4], gpp = kGamma * Wp[4];
+  const double cm = gm * rsq_pos(gm * Wm[0]);
+  const double cp = gpp * rsq_pos(gpp * Wp[0]);
+  const double ap = fmax(fmax(vnm + cm, vnp + cp), 0.0);
+  const double am = fmin(fmin(vnm - cm, vnp - cp), 0.0);
+  const double inv = recip(ap - am);
+  wm = ap * (vnm - am) * inv;
+  wp = am * (ap - vnp) * inv;
+  const double Em = Wm[4] * kInvGm1 +
+                    0.5 * Wm[0] * (Wm[1] * Wm[1] + Wm[2] * Wm[2] + Wm[3] * Wm[3]);
+  const double Ep = Wp[4] * kInvGm1 +
+                    0.5 * Wp[0] * (Wp[1] * Wp[1] + Wp[2] * Wp[2] + Wp[3] * Wp[3]);
+  const double pt = (ap * Wm[4] - am * Wp[4]) * inv;
+  Fh[0] = wm * Wm[0] + wp * Wp[0];
+#pragma unroll
+  for (int k = 1; k <= 3; ++k) {
+    if (k == 1 + DIR)
+      Fh[k] = wm * (Wm[0] * Wm[k]) + wp * (Wp[0] * Wp[k]) + pt;
+    else
+      Fh[k] = wm * (Wm[0] * Wm[k]) + wp * (Wp[0] * Wp[k]);
+  }
+  Fh[4] = wm * Em + wp * Ep + (ap * (Wm[4] * vnm) - am * (Wp[4] * vnp)) * inv;
+  return fmax(ap, -am);
+}
+
 // Face `face` of direction DIR (normal position i, transverse a, b): its
 // Simpson-integrated flux into fh[face * F ..]; returns the largest signal
 // speed of its 9 points.  Points in the order s2 (outer), s1 (inner), weights
@@ -105,7 +139,6 @@ __device__ __forceinline__ void face_lines(int face, int s1, int s2, int (&om)[5
 template <int DIR, int F>
 __device__ __forceinline__ double face26(const double* __restrict__ prim, gcptr u, int face,
                                          double* __restrict__ fh) {
-  constexpr double ex = DIR == 0 ? 1.0 : 0.0, ey = DIR == 1 ? 1.0 : 0.0, ez = DIR == 2 ? 1.0 : 0.0;
   double sum[5], wm[9], wp[9];
 #pragma unroll
   for (int f = 0; f < 5; ++f) sum[f] = 0.0;
@@ -123,7 +156,7 @@ __device__ __forceinline__ double face26(const double* __restrict__ prim, gcptr 
     point_core(prim, om, Wm);
     __builtin_amdgcn_sched_barrier(0);
     point_core(prim, op, Wp);
-    smax = fmax(smax, core_flux(Wm, Wp, ex, ey, ez, Fh, wm[p], wp[p]));
+    smax = fmax(smax, core_flux_axis<DIR>(Wm, Wp, Fh, wm[p], wp[p]));
     const double w = (s1 == 0 && s2 == 0) ? 16.0 : (s1 == 0 || s2 == 0) ? 4.0 : 1.0;
 #pragma unroll
     for (int f = 0; f < 5; ++f) sum[f] = sum[f] + w * Fh[f];
